@@ -1,0 +1,153 @@
+"""CPU oracle for chunked multi-byte LZSS (gpuLZ, Zhang et al., ICS'23).
+
+TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package. The product library
+(``paper_2304_07342_amd``) never imports, loads or calls it, and the two
+share no code.
+
+The oracle is plain C99 (``gpulz_oracle.c``) built with gcc into
+``libgpulz_oracle.so`` and loaded here with ctypes. See the C header for what
+it computes and which passage of the paper each step follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gpulz_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libgpulz_oracle.so")
+
+OK = 0
+ERR_INVALID_ARG = 1
+ERR_OUT_OF_SPACE = 2
+ERR_CORRUPT = 3
+ERR_NOMEM = 7
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no vectorisation pragmas)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-shared", "-fPIC",
+             "-pthread", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.oracle_compress_bound.restype = ctypes.c_uint64
+        lib.oracle_compress_bound.argtypes = [ctypes.c_uint64, ctypes.c_uint32,
+                                              ctypes.c_uint32, ctypes.c_uint32]
+        lib.oracle_compress.restype = ctypes.c_int
+        lib.oracle_compress.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_uint32, ctypes.c_uint32, u8p, ctypes.c_uint64,
+                                        u64p]
+        lib.oracle_compress_mt.restype = ctypes.c_int
+        lib.oracle_compress_mt.argtypes = lib.oracle_compress.argtypes + [ctypes.c_int]
+        lib.oracle_decompress.restype = ctypes.c_int
+        lib.oracle_decompress.argtypes = [u8p, ctypes.c_uint64, u8p, ctypes.c_uint64, u64p]
+        lib.oracle_parse_chunk.restype = ctypes.c_int64
+        lib.oracle_parse_chunk.argtypes = [u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                           ctypes.c_uint32, u32p, u32p]
+        _lib = lib
+    return _lib
+
+
+def _u8(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def _as_bytes(data) -> np.ndarray:
+    if isinstance(data, np.ndarray):
+        return np.ascontiguousarray(data).view(np.uint8).reshape(-1)
+    return np.frombuffer(bytes(data), dtype=np.uint8)
+
+
+def compress_bound(nbytes: int, symbol_bytes: int, chunk_symbols: int, min_match: int) -> int:
+    return int(_load().oracle_compress_bound(nbytes, symbol_bytes, chunk_symbols, min_match))
+
+
+def compress_status(data, symbol_bytes: int, chunk_symbols: int, window: int, min_match: int,
+                    capacity: int | None = None, threads: int = 1):
+    """Return (status, stream_bytes_or_None, required_size)."""
+    lib = _load()
+    x = _as_bytes(data)
+    n = x.size
+    bound = lib.oracle_compress_bound(n, symbol_bytes, chunk_symbols, min_match)
+    cap = bound if capacity is None else capacity
+    out = np.zeros(max(cap, 1), dtype=np.uint8)
+    out_len = ctypes.c_uint64(0)
+    xin = x if n else np.zeros(1, dtype=np.uint8)
+    if threads > 1:
+        st = lib.oracle_compress_mt(_u8(xin), n, symbol_bytes, chunk_symbols, window, min_match,
+                                    _u8(out), cap, ctypes.byref(out_len), threads)
+    else:
+        st = lib.oracle_compress(_u8(xin), n, symbol_bytes, chunk_symbols, window, min_match,
+                                 _u8(out), cap, ctypes.byref(out_len))
+    if st == OK:
+        return st, out[: out_len.value].tobytes(), out_len.value
+    return st, None, out_len.value
+
+
+def compress(data, symbol_bytes: int, chunk_symbols: int, window: int, min_match: int,
+             threads: int = 1) -> bytes:
+    st, stream, _ = compress_status(data, symbol_bytes, chunk_symbols, window, min_match,
+                                    threads=threads)
+    if st != OK:
+        raise ValueError(f"oracle_compress failed with status {st}")
+    return stream
+
+
+def decompress_status(stream, capacity: int | None = None):
+    """Return (status, original_bytes_or_None, n)."""
+    lib = _load()
+    s = _as_bytes(stream)
+    if capacity is None:
+        capacity = int.from_bytes(bytes(s[16:24]), "little") if s.size >= 64 else 0
+        capacity = min(capacity, 1 << 34)
+    out = np.zeros(max(capacity, 1), dtype=np.uint8)
+    out_len = ctypes.c_uint64(0)
+    sin = s if s.size else np.zeros(1, dtype=np.uint8)
+    st = lib.oracle_decompress(_u8(sin), s.size, _u8(out), capacity, ctypes.byref(out_len))
+    if st == OK:
+        return st, out[: out_len.value].tobytes(), out_len.value
+    return st, None, out_len.value
+
+
+def decompress(stream) -> bytes:
+    st, data, _ = decompress_status(stream)
+    if st != OK:
+        raise ValueError(f"oracle_decompress failed with status {st}")
+    return data
+
+
+def parse_chunk(chunk, symbol_bytes: int, window: int, min_match: int):
+    """Tokens of one chunk as a list of (length, offset); length 0 = literal."""
+    lib = _load()
+    x = _as_bytes(chunk)
+    c = x.size // symbol_bytes
+    lengths = np.zeros(max(c, 1), dtype=np.uint32)
+    offsets = np.zeros(max(c, 1), dtype=np.uint32)
+    xin = x if x.size else np.zeros(1, dtype=np.uint8)
+    t = lib.oracle_parse_chunk(_u8(xin), c, symbol_bytes, window, min_match,
+                               lengths.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                               offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    if t < 0:
+        raise ValueError("invalid parameters")
+    return [(int(lengths[i]), int(offsets[i])) for i in range(t)]
