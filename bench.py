@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Benchmark: single-buffer compression of the 256 MiB float32 field.
+
+One step = one gpulz_compress call over the whole input already resident in
+HBM (chunk encode with the longest-match search, global prefix sum + header,
+record compaction). Prints one JSON line.
+
+Workload: float32 field 512 x 512 x 256 (sum of 8 random plane waves plus
+N(0, 1e-3) noise, quantised to 1e-4), 4-byte symbols, chunk 4096 symbols,
+window 256, minimum match 2 (seed 1).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+# 256 CUs x 64 lanes x 2.4 GHz: one 32-bit compare per lane per clock.
+ALU_PEAK_TCMP = 256 * 64 * 2.4e9 / 1e12
+
+
+def window_compares(m: int, C: int, W: int) -> int:
+    """Symbol comparisons of an exhaustive window search: every position j of
+    a chunk is compared with each of the min(j, W) symbols before it."""
+    def per_chunk(c):
+        if c <= W + 1:
+            return c * (c - 1) // 2
+        return W * (W + 1) // 2 + (c - 1 - W) * W
+    full, last = divmod(m, C)
+    return full * per_chunk(C) + (per_chunk(last) if last else 0)
+
+
+def cpu_baseline(x: np.ndarray, S: int, C: int, W: int, MIN: int, sample_bytes: int):
+    import oracle
+    oracle.build(force=False)
+    sample = x[:sample_bytes]
+    t0 = time.perf_counter()
+    oracle.compress(sample, S, C, W, MIN)
+    dt = time.perf_counter() - t0
+    return {"value": round(sample.size / dt / 1e9, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample.size >> 20} MiB ({sample.size // (C * S)} chunks) of the same "
+                      f"input, single-threaded C oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-mib", type=int, default=128)
+    ap.add_argument("--skip-decompress", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only; multi-GPU runs are not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2304_07342_amd import gpulz, synth
+
+    cfg = synth.CONFIGS[1]
+    S, C, W, MIN = cfg["S"], cfg["C"], cfg["W"], cfg["MIN"]
+    print(f"[bench] generating {cfg['name']}", file=sys.stderr, flush=True)
+    x = cfg["make"]().view(np.uint8).reshape(-1)
+    n = x.size
+    d_in = torch.from_numpy(x).to("cuda")
+    comp = gpulz.Compressor(n, S, C, W, MIN)
+    torch.cuda.synchronize()
+
+    print("[bench] warmup", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        comp.compress_async(d_in)
+    size, status = comp.result()
+    if status != gpulz.GPULZ_OK:
+        raise SystemExit(f"compress failed: {gpulz.status_string(status)}")
+
+    print("[bench] timed steps", file=sys.stderr, flush=True)
+    gpulz.gpulz_profile_enable(True)
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        comp.compress_async(d_in)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    prof = gpulz.gpulz_profile_read()
+    gpulz.gpulz_profile_enable(False)
+    ms_step = start.elapsed_time(stop) / args.steps
+    size, status = comp.result()
+    assert status == gpulz.GPULZ_OK
+
+    # exact round trip of the produced stream (outside the timed region)
+    print("[bench] verify + decompress", file=sys.stderr, flush=True)
+    dec_gbps = None
+    if not args.skip_decompress:
+        st_t = comp.out[:size]
+        d = gpulz.decompress(st_t)
+        if not torch.equal(d, d_in):
+            raise SystemExit("round trip mismatch")
+        ws_bytes = gpulz.gpulz_decompress_workspace_size(size)
+        out = torch.empty(n, dtype=torch.uint8, device="cuda")
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        meta = torch.zeros(2, dtype=torch.int64, device="cuda")
+        for _ in range(2):
+            gpulz.gpulz_decompress(st_t.data_ptr(), size, out.data_ptr(), n, meta.data_ptr(),
+                                   meta.data_ptr() + 8, ws.data_ptr(), ws_bytes, stream.cuda_stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        reps = max(3, args.steps // 2)
+        for _ in range(reps):
+            gpulz.gpulz_decompress(st_t.data_ptr(), size, out.data_ptr(), n, meta.data_ptr(),
+                                   meta.data_ptr() + 8, ws.data_ptr(), ws_bytes, stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dec_gbps = n / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
+
+    enc_ms, enc_launches = prof["encode"]
+    enc_avg_ms = enc_ms / max(1, enc_launches)
+    m = n // S
+    compares = window_compares(m, C, W)
+    achieved = compares / (enc_avg_ms / 1e3) / 1e12
+    kernel_ms = {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items() if v[1]}
+    value = n / (ms_step / 1e3) / 1e9
+
+    result = {
+        "metric": "compress GB/s (input) + ratio at 1 GPU; batched GB/s and p99 latency vs plain",
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "field-f32-256MiB: float32 512x512x256, 8 plane waves + N(0,1e-3) "
+                               "noise quantised to 1e-4, seed 1",
+                   "symbol_bytes": S, "chunk_symbols": C, "window": W, "min_match": MIN,
+                   "input_bytes": n},
+        "ratio": round(n / size, 4),
+        "stream_bytes": size,
+        "decompress_GBps": round(dec_gbps, 3) if dec_gbps else None,
+        "kernel_avg_ms": kernel_ms,
+        "hbm_frac_whole_step": round((n + size) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "roofline": {"bound": "alu", "kernel": "encode_kernel<4,4> (match search + parse + encode)",
+                     "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TCMP, 3),
+                     "unit": "Tcmp/s", "frac": round(achieved / ALU_PEAK_TCMP, 4),
+                     "traffic": None, "compares_per_launch": compares},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(x, S, C, W, MIN, args.cpu_sample_mib << 20)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

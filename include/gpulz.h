@@ -1,0 +1,150 @@
+/*
+ * gpulz — chunked multi-byte LZSS compression on AMD Instinct MI355X (gfx950).
+ *
+ * The method is gpuLZ (Zhang, Tian, Di, Yu, Swany, Tao, Cappello, ICS'23):
+ *   - the input is split into independent chunks of C symbols; no match
+ *     crosses a chunk boundary (section 3.3.1, data chunks);
+ *   - symbols are S = 1, 2, 4 or 8 bytes and matching compares whole symbols
+ *     (section 3.2.3, multi-byte matching);
+ *   - inside a chunk, the greedy LZSS parse of section 2.2 (basic steps 1-6)
+ *     takes the longest match in a sliding window of W symbols; a match of
+ *     at least `min_match` symbols becomes a 2-byte pointer, anything else a
+ *     literal (section 3.3.2, encoding step); a match never exceeds its
+ *     offset (section 3.3.2) nor 255 symbols (one-byte fields, section 2.2);
+ *     among equally long matches the largest offset wins;
+ *   - per-token sizes are prefix-summed inside each chunk, the chunk sizes
+ *     across chunks, and the chunk records are compacted into one stream
+ *     (section 3.2.2, two-pass prefix sum; section 3.3.4, deflating).
+ *
+ * Stream layout (little-endian), identical for every producer:
+ *   bytes 0..63   header:
+ *       0  u8[4] magic "GLZ1"       4  u16 version = 1
+ *       6  u8    S                  7  u8  match policy = 0 (exact longest)
+ *       8  u32   C (chunk symbols) 12  u16 W (window symbols, 1..256)
+ *      14  u8    min_match         15  u8  max_match = 255
+ *      16  u64   n (input bytes)   24  u64 N = ceil((n / S) / C) chunks
+ *      32  u64   total stream bytes
+ *      40  u8    r = n mod S       41..47 zero
+ *      48  u8[8] the last r input bytes, zero padded   56..63 zero
+ *   64 .. 64+8N  table: per chunk {u32 flag_bytes F_i, u32 payload_bytes P_i}
+ *   then the records of chunks 0..N-1 back to back, each F_i flag bytes
+ *   followed by P_i payload bytes. Flag bit t of a chunk (bit t & 7 of byte
+ *   t >> 3) is 1 if token t is a pointer; F_i = ceil(T_i / 8), unused bits 0.
+ *   A literal's payload is its S raw bytes; a pointer's is
+ *   [length][offset & 0xFF] (offset 256 is stored as 0).
+ *
+ * Conventions for every entry point below:
+ *   - Device pointers (d_*) are caller-owned device memory (for instance
+ *     torch tensors). The library never allocates or frees on the
+ *     compress/decompress paths; it only launches kernels on `stream`.
+ *   - d_in and d_out must be 16-byte aligned; d_workspace 256-byte aligned.
+ *   - Sizes are in bytes; chunk_symbols, window and min_match in symbols.
+ *   - The return value reports host-detectable problems only (invalid
+ *     argument, workspace too small, chunk too large for on-chip memory,
+ *     a failed HIP launch). Outcomes that depend on the data are written on
+ *     the stream to *d_status (a gpulz_status) and *d_out_bytes; read them
+ *     after synchronising the stream.
+ *   - Calls on different streams with distinct workspaces may overlap.
+ */
+#ifndef GPULZ_H
+#define GPULZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GPULZ_OK = 0,
+  GPULZ_ERR_INVALID_ARG = 1,
+  GPULZ_ERR_OUT_OF_SPACE = 2,
+  GPULZ_ERR_CORRUPT = 3,
+  GPULZ_ERR_WORKSPACE = 4,
+  GPULZ_ERR_HIP = 5,
+  GPULZ_ERR_UNSUPPORTED = 6
+} gpulz_status;
+
+/* Version of this interface (major * 100 + minor). */
+uint32_t gpulz_abi_version(void);
+
+/* Static string naming a status code ("unknown status" for other values). */
+const char* gpulz_status_string(int32_t status);
+
+/* Largest stream gpulz_compress can produce for these parameters: header,
+ * table, and for every chunk of c symbols ceil(c/8) flag bytes plus c*k
+ * payload bytes, k = 2 if S == 1 and min_match == 1 (every token a pointer)
+ * else S (every token a literal). Returns 0 if the parameters are invalid.
+ * Host-only, pure. */
+uint64_t gpulz_compress_bound(uint64_t nbytes, uint32_t symbol_bytes, uint32_t chunk_symbols,
+                              uint32_t min_match);
+
+/* Workspace bytes gpulz_compress needs for an input of `nbytes`. Host-only.
+ * Returns GPULZ_ERR_INVALID_ARG for invalid parameters or a NULL ws_bytes. */
+gpulz_status gpulz_compress_workspace_size(uint64_t nbytes, uint32_t symbol_bytes,
+                                           uint32_t chunk_symbols, size_t* ws_bytes);
+
+/* Compress d_in[0..nbytes) into d_out as one stream (layout above).
+ *   symbol_bytes  S in {1, 2, 4, 8}
+ *   chunk_symbols C >= 1; the chunk must fit in on-chip memory
+ *                 (C * S <= 60 KiB), else GPULZ_ERR_UNSUPPORTED
+ *   window        W in [1, 256]
+ *   min_match     in [1, 255]
+ *   out_capacity  bytes available at d_out
+ *   d_out_bytes   device u64: receives the stream size (also when it does
+ *                 not fit)
+ *   d_status      device i32: GPULZ_OK, or GPULZ_ERR_OUT_OF_SPACE if the
+ *                 stream is larger than out_capacity (then nothing is
+ *                 written to d_out)
+ *   d_workspace   at least gpulz_compress_workspace_size bytes
+ * Asynchronous on `stream` (0 = null stream). Same bytes as any other
+ * conforming producer for the same input and parameters. */
+gpulz_status gpulz_compress(const void* d_in, uint64_t nbytes, uint32_t symbol_bytes,
+                            uint32_t chunk_symbols, uint32_t window, uint32_t min_match,
+                            void* d_out, uint64_t out_capacity, uint64_t* d_out_bytes,
+                            int32_t* d_status, void* d_workspace, size_t ws_bytes,
+                            hipStream_t stream);
+
+/* Read the fields of a stream header from a host copy of its first 64 bytes.
+ * Validates magic, version and field ranges; GPULZ_ERR_CORRUPT otherwise.
+ * Any output pointer may be NULL. Host-only. */
+gpulz_status gpulz_peek_header(const void* h_header, size_t header_bytes, uint64_t* nbytes,
+                               uint32_t* symbol_bytes, uint64_t* stream_bytes);
+
+/* Workspace bytes gpulz_decompress needs for a stream of `stream_bytes`.
+ * Host-only. */
+gpulz_status gpulz_decompress_workspace_size(uint64_t stream_bytes, size_t* ws_bytes);
+
+/* Decompress the stream d_in[0..in_bytes) into d_out. The decoder checks
+ * every rule of the layout (header fields, table sums, flag and payload
+ * extents, each pointer within 1..W, within the symbols already decoded in
+ * its chunk, not longer than its offset and not past the chunk end, unused
+ * flag bits zero). On the stream it writes *d_status = GPULZ_OK,
+ * GPULZ_ERR_CORRUPT (a rule is broken; d_out contents are then
+ * unspecified) or GPULZ_ERR_OUT_OF_SPACE (out_capacity < n; nothing is
+ * written to d_out), and *d_out_bytes = n from a valid header (0 if the
+ * header is invalid). Asynchronous on `stream`. */
+gpulz_status gpulz_decompress(const void* d_in, uint64_t in_bytes, void* d_out,
+                              uint64_t out_capacity, uint64_t* d_out_bytes, int32_t* d_status,
+                              void* d_workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Kernel timing for benchmarks. While enabled, every gpulz_compress and
+ * gpulz_decompress call records a pair of HIP events on its own stream
+ * around each kernel it launches, so the times cover exactly those kernels.
+ * Kernel ids: 0 chunk encode, 1 global scan + header, 2 record scatter,
+ * 3 decode prepare (header check + table scan), 4 chunk decode.
+ * gpulz_profile_enable(1) clears the accumulated times, (0) stops recording.
+ * gpulz_profile_read waits for the recorded events and writes, for each of
+ * the first `nkernels` ids, the summed milliseconds and the launch count
+ * (either pointer may be NULL). Host-side; not for concurrent use. */
+gpulz_status gpulz_profile_enable(int enable);
+gpulz_status gpulz_profile_read(double* total_ms, uint64_t* launches, int nkernels);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPULZ_H */

@@ -1,0 +1,246 @@
+// C ABI: argument checks, workspace layout, kernel launches.
+#include "gpulz.h"
+
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "gpulz_internal.h"
+
+using namespace gpulz;
+
+namespace {
+
+// ---- optional per-kernel event timing ---------------------------------------
+constexpr int kProfKernels = 5;
+struct EventPair {
+  int kernel;
+  hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<EventPair> g_prof_events;
+
+// Records `start` before a launch when profiling; returns the pair index or -1.
+int prof_begin(int kernel, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on) return -1;
+  EventPair e{kernel, nullptr, nullptr};
+  if (hipEventCreate(&e.start) != hipSuccess || hipEventCreate(&e.stop) != hipSuccess) return -1;
+  hipEventRecord(e.start, s);
+  g_prof_events.push_back(e);
+  return (int)g_prof_events.size() - 1;
+}
+
+void prof_end(int idx, hipStream_t s) {
+  if (idx < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEventRecord(g_prof_events[idx].stop, s);
+}
+
+bool valid_params(uint32_t S, uint32_t C, uint32_t W, uint32_t MIN) {
+  if (!(S == 1 || S == 2 || S == 4 || S == 8)) return false;
+  if (C < 1 || C > (1u << 24)) return false;
+  if (W < 1 || W > kMaxWindow) return false;
+  if (MIN < 1 || MIN > kMaxMatch) return false;
+  return true;
+}
+
+bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+uint64_t num_chunks(uint64_t nbytes, uint32_t S, uint32_t C) {
+  const uint64_t m = nbytes / S;
+  return (m + C - 1) / C;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t gpulz_abi_version(void) { return 100; }
+
+const char* gpulz_status_string(int32_t status) {
+  switch (status) {
+    case GPULZ_OK: return "ok";
+    case GPULZ_ERR_INVALID_ARG: return "invalid argument";
+    case GPULZ_ERR_OUT_OF_SPACE: return "output capacity too small";
+    case GPULZ_ERR_CORRUPT: return "corrupt stream";
+    case GPULZ_ERR_WORKSPACE: return "workspace too small";
+    case GPULZ_ERR_HIP: return "HIP runtime error";
+    case GPULZ_ERR_UNSUPPORTED: return "unsupported on this device";
+    default: return "unknown status";
+  }
+}
+
+uint64_t gpulz_compress_bound(uint64_t nbytes, uint32_t S, uint32_t C, uint32_t MIN) {
+  if (!valid_params(S, C, 1, MIN)) return 0;
+  const uint64_t m = nbytes / S;
+  const uint64_t k = (S == 1 && MIN == 1) ? 2 : S;
+  const uint64_t full = m / C, last = m % C;
+  uint64_t total = kHeaderBytes + 8 * num_chunks(nbytes, S, C);
+  total += full * ((C + 7) / 8 + (uint64_t)C * k);
+  if (last) total += (last + 7) / 8 + last * k;
+  return total;
+}
+
+gpulz_status gpulz_compress_workspace_size(uint64_t nbytes, uint32_t S, uint32_t C,
+                                           size_t* ws_bytes) {
+  if (!ws_bytes || !valid_params(S, C, 1, 1)) return GPULZ_ERR_INVALID_ARG;
+  // the slot size depends on min_match only for S == 1; size for the worst
+  *ws_bytes = (size_t)compress_workspace(num_chunks(nbytes, S, C), C, S, 1).total;
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_compress(const void* d_in, uint64_t nbytes, uint32_t S, uint32_t C, uint32_t W,
+                            uint32_t MIN, void* d_out, uint64_t out_capacity, uint64_t* d_out_bytes,
+                            int32_t* d_status, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  if (!valid_params(S, C, W, MIN)) return GPULZ_ERR_INVALID_ARG;
+  if ((nbytes && !d_in) || !d_out_bytes || !d_status || (out_capacity && !d_out))
+    return GPULZ_ERR_INVALID_ARG;
+  if (!aligned(d_in, 16) || !aligned(d_out, 16) || !aligned(d_ws, 256)) return GPULZ_ERR_INVALID_ARG;
+  if ((uint64_t)C * S > kMaxChunkBytes) return GPULZ_ERR_UNSUPPORTED;
+  const uint64_t N = num_chunks(nbytes, S, C);
+  const CompressWorkspace w = compress_workspace(N, C, S, 1);
+  if (!d_ws || ws_bytes < w.total) return GPULZ_ERR_WORKSPACE;
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  const SlotLayout sl = slot_layout(C, S, 1);
+
+  EncodeArgs e;
+  e.in = static_cast<const uint8_t*>(d_in);
+  e.nbytes = nbytes;
+  e.m = nbytes / S;
+  e.C = C;
+  e.W = W;
+  e.MIN = MIN;
+  e.slots = ws + w.slots_off;
+  e.slot_bytes = sl.slot_bytes;
+  e.flag_area = sl.flag_area;
+  e.sizes = reinterpret_cast<uint32_t*>(ws + w.sizes_off);
+  int pi = prof_begin(0, stream);
+  if (launch_encode(e, S, N, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  prof_end(pi, stream);
+
+  ScanArgs sa;
+  sa.sizes = e.sizes;
+  sa.N = N;
+  sa.offsets = reinterpret_cast<uint64_t*>(ws + w.offsets_off);
+  sa.in = e.in;
+  sa.nbytes = nbytes;
+  sa.S = S;
+  sa.C = C;
+  sa.W = W;
+  sa.MIN = MIN;
+  sa.out = static_cast<uint8_t*>(d_out);
+  sa.capacity = out_capacity;
+  sa.out_bytes = d_out_bytes;
+  sa.status = d_status;
+  pi = prof_begin(1, stream);
+  if (launch_scan(sa, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  prof_end(pi, stream);
+
+  ScatterArgs sc;
+  sc.sizes = e.sizes;
+  sc.offsets = sa.offsets;
+  sc.N = N;
+  sc.slots = e.slots;
+  sc.slot_bytes = sl.slot_bytes;
+  sc.flag_area = sl.flag_area;
+  sc.out = sa.out;
+  sc.capacity = out_capacity;
+  pi = prof_begin(2, stream);
+  if (launch_scatter(sc, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  prof_end(pi, stream);
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_peek_header(const void* h_header, size_t header_bytes, uint64_t* nbytes,
+                               uint32_t* symbol_bytes, uint64_t* stream_bytes) {
+  if (!h_header || header_bytes < kHeaderBytes) return GPULZ_ERR_INVALID_ARG;
+  const uint8_t* h = static_cast<const uint8_t*>(h_header);
+  if (memcmp(h, "GLZ1", 4) != 0 || h[4] != 1 || h[5] != 0) return GPULZ_ERR_CORRUPT;
+  uint64_t n = 0, total = 0;
+  uint32_t C = 0;
+  for (int k = 7; k >= 0; --k) n = (n << 8) | h[16 + k];
+  for (int k = 7; k >= 0; --k) total = (total << 8) | h[32 + k];
+  for (int k = 3; k >= 0; --k) C = (C << 8) | h[8 + k];
+  const uint32_t W = (uint32_t)h[12] | ((uint32_t)h[13] << 8);
+  if (!valid_params(h[6], C, W, h[14]) || h[7] != 0 || h[15] != kMaxMatch) return GPULZ_ERR_CORRUPT;
+  if (nbytes) *nbytes = n;
+  if (symbol_bytes) *symbol_bytes = h[6];
+  if (stream_bytes) *stream_bytes = total;
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_decompress_workspace_size(uint64_t stream_bytes, size_t* ws_bytes) {
+  if (!ws_bytes) return GPULZ_ERR_INVALID_ARG;
+  *ws_bytes = (size_t)(256 + 8 * (decode_max_chunks(stream_bytes) + 1));
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_decompress(const void* d_in, uint64_t in_bytes, void* d_out, uint64_t out_capacity,
+                              uint64_t* d_out_bytes, int32_t* d_status, void* d_ws, size_t ws_bytes,
+                              hipStream_t stream) {
+  if ((in_bytes && !d_in) || !d_out_bytes || !d_status || (out_capacity && !d_out))
+    return GPULZ_ERR_INVALID_ARG;
+  if (!aligned(d_in, 16) || !aligned(d_out, 16) || !aligned(d_ws, 256)) return GPULZ_ERR_INVALID_ARG;
+  size_t need = 0;
+  gpulz_decompress_workspace_size(in_bytes, &need);
+  if (!d_ws || ws_bytes < need) return GPULZ_ERR_WORKSPACE;
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  DecodePrepArgs pa;
+  pa.in = static_cast<const uint8_t*>(d_in);
+  pa.in_bytes = in_bytes;
+  pa.capacity = out_capacity;
+  pa.max_chunks = decode_max_chunks(in_bytes);
+  pa.params = reinterpret_cast<DecodeParams*>(ws);
+  pa.offsets = reinterpret_cast<uint64_t*>(ws + 256);
+  pa.out_bytes = d_out_bytes;
+  pa.status = d_status;
+  DecodeArgs da;
+  da.in = pa.in;
+  da.params = pa.params;
+  da.offsets = pa.offsets;
+  da.out = static_cast<uint8_t*>(d_out);
+  da.status = d_status;
+  int pi = prof_begin(3, stream);
+  if (launch_decode_prepare(pa, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  prof_end(pi, stream);
+  pi = prof_begin(4, stream);
+  if (launch_decode_chunks(da, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  prof_end(pi, stream);
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_profile_enable(int enable) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& e : g_prof_events) {
+    hipEventSynchronize(e.stop);
+    hipEventDestroy(e.start);
+    hipEventDestroy(e.stop);
+  }
+  g_prof_events.clear();
+  g_prof_on = enable != 0;
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_profile_read(double* total_ms, uint64_t* launches, int nkernels) {
+  if (nkernels < 0) return GPULZ_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double ms[kProfKernels] = {0};
+  uint64_t cnt[kProfKernels] = {0};
+  for (auto& e : g_prof_events) {
+    float t = 0.f;
+    if (hipEventSynchronize(e.stop) != hipSuccess) return GPULZ_ERR_HIP;
+    if (hipEventElapsedTime(&t, e.start, e.stop) != hipSuccess) return GPULZ_ERR_HIP;
+    ms[e.kernel] += t;
+    cnt[e.kernel] += 1;
+  }
+  for (int k = 0; k < nkernels && k < kProfKernels; ++k) {
+    if (total_ms) total_ms[k] = ms[k];
+    if (launches) launches[k] = cnt[k];
+  }
+  return GPULZ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// Internal declarations shared by the HIP kernel files and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpulz {
+
+constexpr uint32_t kHeaderBytes = 64;
+constexpr uint32_t kMaxMatch = 255;
+constexpr uint32_t kMaxWindow = 256;
+// Largest chunk (in bytes) the encoder stages in LDS.
+constexpr uint32_t kMaxChunkBytes = 60 * 1024;
+// Per-wave LDS ring the decoder rebuilds symbols in (independent of C).
+constexpr uint32_t kDecodeRingBytes = 16 * 1024;
+
+// Device status values (same numbering as gpulz_status).
+enum : int32_t { kOk = 0, kOutOfSpace = 2, kCorrupt = 3 };
+
+__host__ __device__ constexpr uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+// ---- compress ---------------------------------------------------------------
+
+// Per-chunk scratch record laid out as [flag area | payload area | slack].
+struct SlotLayout {
+  uint64_t flag_area;   // bytes reserved for flags (multiple of 16)
+  uint64_t slot_bytes;  // full slot (multiple of 16)
+};
+
+__host__ __device__ inline SlotLayout slot_layout(uint32_t C, uint32_t S, uint32_t min_match) {
+  const uint64_t k = (S == 1 && min_match == 1) ? 2 : S;
+  SlotLayout l;
+  l.flag_area = align_up(align_up(C, 64) / 8, 16);
+  l.slot_bytes = align_up(l.flag_area + (uint64_t)C * k + 16, 16);
+  return l;
+}
+
+// Workspace = sizes[N] (u32 F, u32 P) | offsets[N+1] (u64) | slots[N].
+struct CompressWorkspace {
+  uint64_t sizes_off, offsets_off, slots_off, total;
+};
+
+__host__ __device__ inline CompressWorkspace compress_workspace(uint64_t N, uint32_t C, uint32_t S,
+                                                                uint32_t min_match) {
+  CompressWorkspace w;
+  w.sizes_off = 0;
+  w.offsets_off = align_up(8 * N, 256);
+  w.slots_off = w.offsets_off + align_up(8 * (N + 1), 256);
+  w.total = w.slots_off + N * slot_layout(C, S, min_match).slot_bytes + 256;
+  return w;
+}
+
+struct EncodeArgs {
+  const uint8_t* in;
+  uint64_t nbytes;      // input bytes (for bounds of the staging loads)
+  uint64_t m;           // input symbols
+  uint32_t C, W, MIN;
+  uint8_t* slots;
+  uint64_t slot_bytes;
+  uint64_t flag_area;
+  uint32_t* sizes;      // 2 per chunk: F, P
+};
+
+struct ScanArgs {
+  const uint32_t* sizes;
+  uint64_t N;
+  uint64_t* offsets;    // N + 1 entries (exclusive prefix, then the sum)
+  const uint8_t* in;    // for the tail bytes
+  uint64_t nbytes;
+  uint32_t S, C, W, MIN;
+  uint8_t* out;
+  uint64_t capacity;
+  uint64_t* out_bytes;
+  int32_t* status;
+};
+
+struct ScatterArgs {
+  const uint32_t* sizes;
+  const uint64_t* offsets;
+  uint64_t N;
+  const uint8_t* slots;
+  uint64_t slot_bytes;
+  uint64_t flag_area;
+  uint8_t* out;
+  uint64_t capacity;
+};
+
+// Launchers (asynchronous; return the launch's hipError_t).
+hipError_t launch_encode(const EncodeArgs& a, uint32_t S, uint64_t N, hipStream_t s);
+hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
+hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
+size_t encode_lds_bytes(uint32_t C, uint32_t S, uint32_t W);
+
+// ---- decompress -------------------------------------------------------------
+
+struct DecodeParams {
+  int32_t status;
+  uint32_t S, C, W, MIN, r;
+  uint64_t n, m, N;
+};
+
+// Workspace = DecodeParams (256 B) | record offsets[max_chunks + 1] (u64).
+__host__ __device__ inline uint64_t decode_max_chunks(uint64_t stream_bytes) {
+  // every chunk costs at least 8 table bytes, 1 flag byte and 1 payload byte
+  return stream_bytes > kHeaderBytes ? (stream_bytes - kHeaderBytes) / 10 : 0;
+}
+
+struct DecodePrepArgs {
+  const uint8_t* in;
+  uint64_t in_bytes;
+  uint64_t capacity;
+  uint64_t max_chunks;
+  DecodeParams* params;
+  uint64_t* offsets;
+  uint64_t* out_bytes;
+  int32_t* status;
+};
+
+struct DecodeArgs {
+  const uint8_t* in;
+  const DecodeParams* params;
+  const uint64_t* offsets;
+  uint8_t* out;
+  int32_t* status;
+};
+
+hipError_t launch_decode_prepare(const DecodePrepArgs& a, hipStream_t s);
+hipError_t launch_decode_chunks(const DecodeArgs& a, hipStream_t s);
+
+}  // namespace gpulz

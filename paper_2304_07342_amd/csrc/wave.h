@@ -1,0 +1,61 @@
+// Wavefront-64 primitives for CDNA (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpulz {
+
+template <int S> struct SymType;
+template <> struct SymType<1> { using T = uint8_t; };
+template <> struct SymType<2> { using T = uint16_t; };
+template <> struct SymType<4> { using T = uint32_t; };
+template <> struct SymType<8> { using T = uint64_t; };
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// 64-bit mask of the lanes whose predicate holds (a v_cmp result in SGPRs).
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Number of set bits of `m` below this lane.
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, uint32_t lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)lane);
+}
+
+// Inclusive prefix sum across the wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+
+// Orders this wave's LDS and global accesses before the ones that follow
+// (LDS is accessed in order within a wave; this keeps the compiler from
+// moving accesses across the point and waits for outstanding ones).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+}  // namespace gpulz

@@ -1,0 +1,228 @@
+"""Python binding for libgpulz.so (the HIP kernels behind a C ABI).
+
+Argument marshalling only: every step of compression and decompression runs
+in the library's HIP kernels. The raw functions carry the C names and take
+integer device pointers; `compress` / `decompress` wrap them for torch
+tensors on the current HIP stream. There is no CPU fallback: if the library
+is missing, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgpulz.so")
+
+GPULZ_OK = 0
+GPULZ_ERR_INVALID_ARG = 1
+GPULZ_ERR_OUT_OF_SPACE = 2
+GPULZ_ERR_CORRUPT = 3
+GPULZ_ERR_WORKSPACE = 4
+GPULZ_ERR_HIP = 5
+GPULZ_ERR_UNSUPPORTED = 6
+
+# Every symbol the C header declares.
+EXPORTS = (
+    "gpulz_abi_version", "gpulz_status_string", "gpulz_compress_bound",
+    "gpulz_compress_workspace_size", "gpulz_compress", "gpulz_peek_header",
+    "gpulz_decompress_workspace_size", "gpulz_decompress", "gpulz_profile_enable",
+    "gpulz_profile_read",
+)
+KERNEL_NAMES = ("encode", "scan", "scatter", "decode_prepare", "decode")
+
+
+class GpulzError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2304_07342_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        u32, u64, i32, sz, vp = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t,
+                                 ctypes.c_void_p)
+        L.gpulz_abi_version.restype = u32
+        L.gpulz_abi_version.argtypes = []
+        L.gpulz_status_string.restype = ctypes.c_char_p
+        L.gpulz_status_string.argtypes = [i32]
+        L.gpulz_compress_bound.restype = u64
+        L.gpulz_compress_bound.argtypes = [u64, u32, u32, u32]
+        L.gpulz_compress_workspace_size.restype = ctypes.c_int
+        L.gpulz_compress_workspace_size.argtypes = [u64, u32, u32, ctypes.POINTER(sz)]
+        L.gpulz_compress.restype = ctypes.c_int
+        L.gpulz_compress.argtypes = [vp, u64, u32, u32, u32, u32, vp, u64, vp, vp, vp, sz, vp]
+        L.gpulz_peek_header.restype = ctypes.c_int
+        L.gpulz_peek_header.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(u64),
+                                        ctypes.POINTER(u32), ctypes.POINTER(u64)]
+        L.gpulz_decompress_workspace_size.restype = ctypes.c_int
+        L.gpulz_decompress_workspace_size.argtypes = [u64, ctypes.POINTER(sz)]
+        L.gpulz_decompress.restype = ctypes.c_int
+        L.gpulz_decompress.argtypes = [vp, u64, vp, u64, vp, vp, vp, sz, vp]
+        L.gpulz_profile_enable.restype = ctypes.c_int
+        L.gpulz_profile_enable.argtypes = [ctypes.c_int]
+        L.gpulz_profile_read.restype = ctypes.c_int
+        L.gpulz_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
+                                         ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+# ---- raw C ABI (same names as include/gpulz.h) ------------------------------
+
+def gpulz_abi_version() -> int:
+    return lib().gpulz_abi_version()
+
+
+def status_string(status: int) -> str:
+    return lib().gpulz_status_string(status).decode()
+
+
+gpulz_status_string = status_string
+
+
+def gpulz_compress_bound(nbytes: int, symbol_bytes: int, chunk_symbols: int, min_match: int) -> int:
+    return lib().gpulz_compress_bound(nbytes, symbol_bytes, chunk_symbols, min_match)
+
+
+def gpulz_compress_workspace_size(nbytes: int, symbol_bytes: int, chunk_symbols: int) -> int:
+    ws = ctypes.c_size_t(0)
+    st = lib().gpulz_compress_workspace_size(nbytes, symbol_bytes, chunk_symbols, ctypes.byref(ws))
+    if st != GPULZ_OK:
+        raise GpulzError(st, "gpulz_compress_workspace_size")
+    return ws.value
+
+
+def gpulz_compress(d_in: int, nbytes: int, symbol_bytes: int, chunk_symbols: int, window: int,
+                   min_match: int, d_out: int, out_capacity: int, d_out_bytes: int, d_status: int,
+                   d_workspace: int, ws_bytes: int, stream: int = 0) -> int:
+    return lib().gpulz_compress(d_in, nbytes, symbol_bytes, chunk_symbols, window, min_match, d_out,
+                                out_capacity, d_out_bytes, d_status, d_workspace, ws_bytes, stream)
+
+
+def gpulz_peek_header(header: bytes):
+    n, s, total = ctypes.c_uint64(0), ctypes.c_uint32(0), ctypes.c_uint64(0)
+    st = lib().gpulz_peek_header(bytes(header), len(header), ctypes.byref(n), ctypes.byref(s),
+                                 ctypes.byref(total))
+    if st != GPULZ_OK:
+        raise GpulzError(st, "gpulz_peek_header")
+    return n.value, s.value, total.value
+
+
+def gpulz_decompress_workspace_size(stream_bytes: int) -> int:
+    ws = ctypes.c_size_t(0)
+    st = lib().gpulz_decompress_workspace_size(stream_bytes, ctypes.byref(ws))
+    if st != GPULZ_OK:
+        raise GpulzError(st, "gpulz_decompress_workspace_size")
+    return ws.value
+
+
+def gpulz_decompress(d_in: int, in_bytes: int, d_out: int, out_capacity: int, d_out_bytes: int,
+                     d_status: int, d_workspace: int, ws_bytes: int, stream: int = 0) -> int:
+    return lib().gpulz_decompress(d_in, in_bytes, d_out, out_capacity, d_out_bytes, d_status,
+                                  d_workspace, ws_bytes, stream)
+
+
+def gpulz_profile_enable(enable: bool) -> None:
+    _check(lib().gpulz_profile_enable(1 if enable else 0), "gpulz_profile_enable")
+
+
+def gpulz_profile_read():
+    """{kernel name: (total ms, launches)} for the calls made while enabled."""
+    n = len(KERNEL_NAMES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_uint64 * n)()
+    _check(lib().gpulz_profile_read(ms, cnt, n), "gpulz_profile_read")
+    return {k: (ms[i], int(cnt[i])) for i, k in enumerate(KERNEL_NAMES)}
+
+
+# ---- torch convenience wrappers --------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _check(st: int, what: str):
+    if st != GPULZ_OK:
+        raise GpulzError(st, what)
+
+
+class Compressor:
+    """Reusable device buffers for compressing inputs of up to `max_bytes`.
+
+    `compress_async` only enqueues kernels on the stream; `result` reads
+    back the size and status (synchronising the stream)."""
+
+    def __init__(self, max_bytes: int, symbol_bytes: int, chunk_symbols: int, window: int,
+                 min_match: int, device="cuda"):
+        torch = _torch()
+        self.S, self.C, self.W, self.MIN = symbol_bytes, chunk_symbols, window, min_match
+        self.capacity = gpulz_compress_bound(max_bytes, symbol_bytes, chunk_symbols, min_match)
+        if self.capacity == 0:
+            raise GpulzError(GPULZ_ERR_INVALID_ARG, "gpulz_compress_bound")
+        self.ws_bytes = gpulz_compress_workspace_size(max_bytes, symbol_bytes, chunk_symbols)
+        self.out = torch.empty(self.capacity, dtype=torch.uint8, device=device)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.meta = torch.zeros(2, dtype=torch.int64, device=device)  # [out_bytes, status]
+
+    def compress_async(self, x, nbytes: int | None = None, stream=None) -> None:
+        nbytes = x.numel() * x.element_size() if nbytes is None else nbytes
+        st = gpulz_compress(x.data_ptr(), nbytes, self.S, self.C, self.W, self.MIN,
+                            self.out.data_ptr(), self.capacity, self.meta.data_ptr(),
+                            self.meta.data_ptr() + 8, self.ws.data_ptr(), self.ws_bytes,
+                            _stream_handle(stream))
+        _check(st, "gpulz_compress")
+
+    def result(self):
+        """(stream bytes, device status)."""
+        meta = self.meta.cpu()
+        return int(meta[0]), int(meta[1]) & 0xFFFFFFFF
+
+
+def compress(x, symbol_bytes: int, chunk_symbols: int, window: int, min_match: int, stream=None):
+    """Compress a device tensor's bytes; returns a uint8 device tensor."""
+    nbytes = x.numel() * x.element_size()
+    c = Compressor(max(nbytes, 1), symbol_bytes, chunk_symbols, window, min_match, device=x.device)
+    c.compress_async(x, nbytes, stream)
+    size, status = c.result()
+    _check(status, "gpulz_compress (device status)")
+    return c.out[:size]
+
+
+def decompress(s, out_capacity: int | None = None, stream=None, return_status: bool = False):
+    """Decompress a uint8 device tensor holding one stream."""
+    torch = _torch()
+    in_bytes = s.numel()
+    if out_capacity is None:
+        hdr = bytes(s[:64].cpu().numpy()) if in_bytes >= 64 else b""
+        try:
+            out_capacity = gpulz_peek_header(hdr)[0]
+        except GpulzError:
+            out_capacity = 0
+    ws_bytes = gpulz_decompress_workspace_size(in_bytes)
+    out = torch.empty(max(out_capacity, 1), dtype=torch.uint8, device=s.device)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=s.device)
+    meta = torch.zeros(2, dtype=torch.int64, device=s.device)
+    st = gpulz_decompress(s.data_ptr(), in_bytes, out.data_ptr(), out_capacity, meta.data_ptr(),
+                          meta.data_ptr() + 8, ws.data_ptr(), ws_bytes, _stream_handle(stream))
+    _check(st, "gpulz_decompress")
+    m = meta.cpu()
+    n, status = int(m[0]), int(m[1]) & 0xFFFFFFFF
+    if return_status:
+        return status, out[:n] if status == GPULZ_OK else None
+    _check(status, "gpulz_decompress (device status)")
+    return out[:n]

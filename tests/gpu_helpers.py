@@ -1,0 +1,70 @@
+"""Helpers for the GPU tests: call the C ABI with torch device buffers."""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2304_07342_amd import gpulz
+
+CANARY = 0xA5
+
+
+def to_device(x: np.ndarray):
+    import torch
+    b = np.ascontiguousarray(x).view(np.uint8).reshape(-1)
+    t = torch.empty(max(b.size, 1), dtype=torch.uint8, device="cuda")
+    if b.size:
+        t[: b.size].copy_(torch.from_numpy(b.copy()))
+    return t
+
+
+def gpu_compress(x, S, C, W, MIN, capacity=None, slack=64):
+    """Run gpulz_compress; returns (status, stream bytes or None, out_bytes,
+    canary_intact). The output buffer has `slack` canary bytes past the
+    capacity to detect writes beyond it."""
+    import torch
+    b = np.ascontiguousarray(x).view(np.uint8).reshape(-1) if isinstance(x, np.ndarray) else \
+        np.frombuffer(bytes(x), dtype=np.uint8)
+    n = b.size
+    d_in = to_device(b)
+    bound = gpulz.gpulz_compress_bound(n, S, C, MIN)
+    cap = bound if capacity is None else capacity
+    out = torch.full((cap + slack,), CANARY, dtype=torch.uint8, device="cuda")
+    ws_bytes = gpulz.gpulz_compress_workspace_size(n, S, C)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    meta = torch.zeros(2, dtype=torch.int64, device="cuda")
+    st = gpulz.gpulz_compress(d_in.data_ptr(), n, S, C, W, MIN, out.data_ptr(), cap,
+                              meta.data_ptr(), meta.data_ptr() + 8, ws.data_ptr(), ws_bytes,
+                              torch.cuda.current_stream().cuda_stream)
+    assert st == gpulz.GPULZ_OK, gpulz.status_string(st)
+    torch.cuda.synchronize()
+    m = meta.cpu().numpy()
+    out_bytes, status = int(m[0]), int(m[1]) & 0xFFFFFFFF
+    host = out.cpu().numpy()
+    canary_ok = bool((host[cap:] == CANARY).all())
+    if status == gpulz.GPULZ_OK:
+        return status, host[:out_bytes].tobytes(), out_bytes, canary_ok
+    untouched = bool((host == CANARY).all())
+    return status, None, out_bytes, canary_ok and untouched
+
+
+def gpu_decompress(stream: bytes, capacity: int, slack=64):
+    """Run gpulz_decompress; returns (status, data or None, out_bytes, canary_intact)."""
+    import torch
+    s = np.frombuffer(bytes(stream), dtype=np.uint8)
+    d_in = to_device(s)
+    out = torch.full((capacity + slack,), CANARY, dtype=torch.uint8, device="cuda")
+    ws_bytes = gpulz.gpulz_decompress_workspace_size(s.size)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    meta = torch.zeros(2, dtype=torch.int64, device="cuda")
+    st = gpulz.gpulz_decompress(d_in.data_ptr(), s.size, out.data_ptr(), capacity, meta.data_ptr(),
+                                meta.data_ptr() + 8, ws.data_ptr(), ws_bytes,
+                                torch.cuda.current_stream().cuda_stream)
+    assert st == gpulz.GPULZ_OK, gpulz.status_string(st)
+    torch.cuda.synchronize()
+    m = meta.cpu().numpy()
+    out_bytes, status = int(m[0]), int(m[1]) & 0xFFFFFFFF
+    host = out.cpu().numpy()
+    canary_ok = bool((host[capacity:] == CANARY).all())
+    if status == gpulz.GPULZ_OK:
+        return status, host[:out_bytes].tobytes(), out_bytes, canary_ok
+    return status, None, out_bytes, canary_ok

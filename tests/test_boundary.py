@@ -1,0 +1,113 @@
+"""The C-ABI library without a GPU: it loads, exports every declared symbol,
+and its host-side queries and argument checks behave as declared."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_2304_07342_amd import gpulz
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "gpulz.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(gpulz_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_what_the_binding_lists():
+    assert declared_functions() == sorted(gpulz.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(gpulz.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_status_strings():
+    assert gpulz.gpulz_abi_version() == 100
+    assert gpulz.status_string(0) == "ok"
+    assert gpulz.status_string(3) == "corrupt stream"
+    assert gpulz.status_string(99) == "unknown status"
+
+
+@pytest.mark.parametrize("n", [0, 1, 7, 1000, 1 << 20, (1 << 20) + 3, 10**9])
+@pytest.mark.parametrize("S,C,MIN", [(1, 2048, 2), (1, 100, 1), (2, 2048, 2), (4, 4096, 2),
+                                     (8, 333, 3)])
+def test_bound_matches_oracle(n, S, C, MIN):
+    assert gpulz.gpulz_compress_bound(n, S, C, MIN) == oracle.compress_bound(n, S, C, MIN)
+
+
+def test_bound_rejects_invalid():
+    assert gpulz.gpulz_compress_bound(100, 3, 16, 2) == 0
+    assert gpulz.gpulz_compress_bound(100, 2, 0, 2) == 0
+    assert gpulz.gpulz_compress_bound(100, 2, 16, 0) == 0
+
+
+def test_workspace_sizes_grow_with_input():
+    a = gpulz.gpulz_compress_workspace_size(1 << 20, 2, 2048)
+    b = gpulz.gpulz_compress_workspace_size(1 << 24, 2, 2048)
+    assert 0 < a < b
+    assert gpulz.gpulz_decompress_workspace_size(1 << 20) < gpulz.gpulz_decompress_workspace_size(1 << 24)
+
+
+def test_peek_header_on_oracle_streams():
+    for S, n in [(1, 0), (2, 11), (4, 4096), (8, 29)]:
+        s = oracle.compress(bytes(range(256)) * (n // 256) + bytes(n % 256), S, 64, 16, 2)
+        assert gpulz.gpulz_peek_header(s[:64]) == (n, S, len(s))
+    with pytest.raises(gpulz.GpulzError):
+        gpulz.gpulz_peek_header(b"GLZ2" + bytes(60))
+    with pytest.raises(gpulz.GpulzError):
+        gpulz.gpulz_peek_header(bytes(10))
+
+
+# Host-detectable errors return before any GPU call, so fake (never
+# dereferenced) pointers are enough to exercise them.
+FAKE = 1 << 40
+
+
+@pytest.mark.parametrize("S,C,W,MIN,code", [
+    (3, 64, 16, 2, gpulz.GPULZ_ERR_INVALID_ARG),
+    (2, 0, 16, 2, gpulz.GPULZ_ERR_INVALID_ARG),
+    (2, 64, 0, 2, gpulz.GPULZ_ERR_INVALID_ARG),
+    (2, 64, 257, 2, gpulz.GPULZ_ERR_INVALID_ARG),
+    (2, 64, 16, 0, gpulz.GPULZ_ERR_INVALID_ARG),
+    (2, 64, 16, 256, gpulz.GPULZ_ERR_INVALID_ARG),
+    (8, 8000, 16, 2, gpulz.GPULZ_ERR_UNSUPPORTED),  # 64000 B chunk > LDS budget
+])
+def test_compress_rejects_bad_parameters(S, C, W, MIN, code):
+    st = gpulz.gpulz_compress(FAKE, 4096, S, C, W, MIN, FAKE, 1 << 20, FAKE, FAKE, FAKE, 1 << 30)
+    assert st == code
+
+
+def test_compress_rejects_misaligned_and_null_pointers():
+    args = dict(S=2, C=64, W=16, MIN=2)
+    st = gpulz.gpulz_compress(FAKE + 4, 4096, 2, 64, 16, 2, FAKE, 1 << 20, FAKE, FAKE, FAKE, 1 << 30)
+    assert st == gpulz.GPULZ_ERR_INVALID_ARG
+    st = gpulz.gpulz_compress(FAKE, 4096, 2, 64, 16, 2, FAKE + 8, 1 << 20, FAKE, FAKE, FAKE, 1 << 30)
+    assert st == gpulz.GPULZ_ERR_INVALID_ARG
+    st = gpulz.gpulz_compress(None, 4096, 2, 64, 16, 2, FAKE, 1 << 20, FAKE, FAKE, FAKE, 1 << 30)
+    assert st == gpulz.GPULZ_ERR_INVALID_ARG
+    st = gpulz.gpulz_compress(FAKE, 4096, 2, 64, 16, 2, FAKE, 1 << 20, None, FAKE, FAKE, 1 << 30)
+    assert st == gpulz.GPULZ_ERR_INVALID_ARG
+    assert args
+
+
+def test_compress_rejects_small_workspace():
+    need = gpulz.gpulz_compress_workspace_size(4096, 2, 64)
+    st = gpulz.gpulz_compress(FAKE, 4096, 2, 64, 16, 2, FAKE, 1 << 20, FAKE, FAKE, FAKE, need - 1)
+    assert st == gpulz.GPULZ_ERR_WORKSPACE
+
+
+def test_decompress_rejects_bad_arguments():
+    need = gpulz.gpulz_decompress_workspace_size(4096)
+    assert gpulz.gpulz_decompress(FAKE, 4096, FAKE, 1 << 20, FAKE, FAKE, FAKE, need - 1) == \
+        gpulz.GPULZ_ERR_WORKSPACE
+    assert gpulz.gpulz_decompress(FAKE + 1, 4096, FAKE, 1 << 20, FAKE, FAKE, FAKE, need) == \
+        gpulz.GPULZ_ERR_INVALID_ARG
+    assert gpulz.gpulz_decompress(FAKE, 4096, FAKE, 1 << 20, FAKE, None, FAKE, need) == \
+        gpulz.GPULZ_ERR_INVALID_ARG

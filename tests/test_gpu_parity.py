@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer work: streams must match byte for byte, decoded data exactly.
+"""
+import random
+import struct
+
+import numpy as np
+import pytest
+
+import oracle
+from golden import all_vectors
+from gpu_helpers import gpu_compress, gpu_decompress
+from paper_2304_07342_amd import gpulz, synth
+
+pytestmark = pytest.mark.gpu
+
+VECTORS = all_vectors()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("v", VECTORS, ids=[v["name"] for v in VECTORS])
+def test_hand_vectors(v):
+    _say("hand vector", v["name"])
+    st, s, _, canary = gpu_compress(v["input"], v["S"], v["C"], v["W"], v["MIN"])
+    assert st == gpulz.GPULZ_OK and canary
+    assert s == oracle.compress(v["input"], v["S"], v["C"], v["W"], v["MIN"])
+    st, d, n, canary = gpu_decompress(s, len(v["input"]))
+    assert st == gpulz.GPULZ_OK and canary and d == v["input"]
+
+
+def _random_case(seed):
+    rng = random.Random(seed)
+    S = rng.choice([1, 2, 4, 8])
+    C = rng.choice([1, 7, 64, 100, 512, 2048, 4096])
+    W = rng.choice([1, 2, 63, 64, 65, 128, 200, 255, 256])
+    MIN = rng.choice([1, 2, 2, 3, 8])
+    n = rng.choice([0, 1, 5, 17, 1000, 30000, 100000, 150001])
+    x = synth.mixed(n, S, seed)
+    return x, S, C, W, MIN
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_parity_and_round_trip(seed):
+    x, S, C, W, MIN = _random_case(seed)
+    _say("random case", seed, "n", x.size, "S", S, "C", C, "W", W, "MIN", MIN)
+    st, s, _, canary = gpu_compress(x, S, C, W, MIN)
+    assert st == gpulz.GPULZ_OK and canary
+    ref = oracle.compress(x, S, C, W, MIN)
+    assert len(s) == len(ref)
+    assert s == ref
+    st, d, n, canary = gpu_decompress(s, x.size)
+    assert st == gpulz.GPULZ_OK and canary and d == x.tobytes()
+
+
+@pytest.mark.parametrize("S", [1, 2, 4, 8])
+@pytest.mark.parametrize("W", [1, 64, 129, 256])
+def test_runs_and_caps(S, W):
+    # long constant and periodic runs: 255 cap, length <= offset, offset 256
+    x = synth.runs(40000 // S, S, seed=S * 1000 + W)
+    _say("runs", S, W)
+    for C in (1000, 4096 // S * 4):
+        st, s, _, _ = gpu_compress(x, S, C, W, 2)
+        assert st == gpulz.GPULZ_OK
+        assert s == oracle.compress(x, S, C, W, 2)
+        st, d, _, _ = gpu_decompress(s, x.size)
+        assert st == gpulz.GPULZ_OK and d == x.tobytes()
+
+
+@pytest.mark.parametrize("S", [1, 2, 4, 8])
+def test_largest_chunk(S):
+    C = 60 * 1024 // S
+    x = synth.mixed(3 * C * S + 7, S, seed=S)
+    _say("largest chunk", S, C)
+    st, s, _, _ = gpu_compress(x, S, C, 256, 2)
+    assert st == gpulz.GPULZ_OK and s == oracle.compress(x, S, C, 256, 2)
+    st, d, _, _ = gpu_decompress(s, x.size)
+    assert st == gpulz.GPULZ_OK and d == x.tobytes()
+
+
+def test_config0_full():
+    cfg = synth.CONFIGS[0]
+    x = cfg["make"]()
+    _say("config0")
+    st, s, _, _ = gpu_compress(x, cfg["S"], cfg["C"], cfg["W"], cfg["MIN"])
+    assert st == gpulz.GPULZ_OK
+    assert s == oracle.compress(x, cfg["S"], cfg["C"], cfg["W"], cfg["MIN"])
+    st, d, _, _ = gpu_decompress(s, x.nbytes)
+    assert st == gpulz.GPULZ_OK and d == x.tobytes()
+
+
+def test_config1_full_size_sampled_chunks():
+    """256 MiB float32 field at full size with the benchmark's parameters.
+    Chunks are independent, so each sampled chunk's table entry and record
+    are checked against the oracle run on that chunk alone; the header,
+    table sums and an exact GPU round trip cover the rest."""
+    import torch
+    cfg = synth.CONFIGS[1]
+    S, C, W, MIN = cfg["S"], cfg["C"], cfg["W"], cfg["MIN"]
+    x = cfg["make"]().view(np.uint8).reshape(-1)
+    _say("config1 full size")
+    c = gpulz.Compressor(x.size, S, C, W, MIN)
+    d_in = torch.from_numpy(x).cuda()
+    c.compress_async(d_in)
+    size, status = c.result()
+    assert status == gpulz.GPULZ_OK
+    s = c.out[:size].cpu().numpy().tobytes()
+    n, SS, total = gpulz.gpulz_peek_header(s[:64])
+    assert (n, SS, total) == (x.size, S, len(s))
+    N = -(-(x.size // S) // C)
+    table = np.frombuffer(s, dtype=np.uint32, count=2 * N, offset=64).reshape(N, 2)
+    offs = 64 + 8 * N + np.concatenate([[0], np.cumsum(table.sum(axis=1).astype(np.int64))])
+    assert offs[-1] == len(s)
+    rng = np.random.default_rng(7)
+    sample = sorted(set(rng.choice(N, size=24, replace=False).tolist()) | {0, N - 1})
+    for i in sample:
+        chunk = x[i * C * S:(i + 1) * C * S]
+        ref = oracle.compress(chunk, S, C, W, MIN)
+        F, P = struct.unpack_from("<II", ref, 64)
+        assert (F, P) == tuple(table[i]), i
+        assert s[offs[i]:offs[i + 1]] == ref[72:72 + F + P], i
+    d = gpulz.decompress(c.out[:size])
+    assert torch.equal(d, d_in)
+
+
+@pytest.mark.parametrize("n,S", [(0, 1), (0, 8), (1, 2), (3, 4), (7, 8), (9, 8), (4097, 4)])
+def test_tiny_and_ragged(n, S):
+    x = synth.mixed(n, S, seed=n + S)
+    _say("tiny", n, S)
+    st, s, _, _ = gpu_compress(x, S, 1024, 64, 2)
+    assert st == gpulz.GPULZ_OK and s == oracle.compress(x, S, 1024, 64, 2)
+    st, d, _, _ = gpu_decompress(s, max(n, 0))
+    assert st == gpulz.GPULZ_OK and d == x.tobytes()
+
+
+def test_compress_out_of_space_writes_nothing():
+    x = synth.mixed(50000, 2, seed=5)
+    ref = oracle.compress(x, 2, 512, 128, 2)
+    _say("out of space")
+    st, s, need, untouched = gpu_compress(x, 2, 512, 128, 2, capacity=len(ref) - 1)
+    assert st == gpulz.GPULZ_ERR_OUT_OF_SPACE and need == len(ref) and untouched
+    st, s, need, canary = gpu_compress(x, 2, 512, 128, 2, capacity=len(ref))
+    assert st == gpulz.GPULZ_OK and s == ref and canary
+
+
+def test_decompress_out_of_space():
+    x = synth.mixed(20000, 4, seed=6)
+    s = oracle.compress(x, 4, 512, 128, 2)
+    st, d, n, canary = gpu_decompress(s, x.size - 1)
+    assert st == gpulz.GPULZ_ERR_OUT_OF_SPACE and n == x.size and canary
+
+
+def test_deterministic_repeats():
+    x = synth.mixed(300000, 4, seed=11)
+    _say("determinism")
+    outs = {gpu_compress(x, 4, 2048, 256, 2)[1] for _ in range(3)}
+    assert len(outs) == 1
+
+
+def _mutations(s, rng, k):
+    for _ in range(k):
+        b = bytearray(s)
+        op = rng.randrange(3)
+        if op == 0:
+            i = rng.randrange(len(b))
+            b[i] ^= 1 << rng.randrange(8)
+        elif op == 1:
+            b = b[:rng.randrange(len(b))]
+        else:
+            i = rng.randrange(64, len(b))
+            b[i] = rng.randrange(256)
+        yield bytes(b)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_decoder_rejects_what_the_oracle_rejects(seed):
+    rng = random.Random(seed)
+    S = [1, 2, 4][seed]
+    x = synth.mixed(3000, S, seed=seed + 50)
+    s = oracle.compress(x, S, 256, 64, 2)
+    _say("decoder fuzz", seed)
+    for mut in _mutations(s, rng, 60):
+        cap = x.size + 64
+        ost, odata, _ = oracle.decompress_status(mut, capacity=cap)
+        gst, gdata, _, canary = gpu_decompress(mut, cap)
+        assert canary
+        if ost == oracle.OK:
+            assert gst == gpulz.GPULZ_OK and gdata == odata
+        else:
+            assert gst != gpulz.GPULZ_OK
