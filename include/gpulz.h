@@ -90,7 +90,7 @@ gpulz_status gpulz_compress_workspace_size(uint64_t nbytes, uint32_t symbol_byte
 /* Compress d_in[0..nbytes) into d_out as one stream (layout above).
  *   symbol_bytes  S in {1, 2, 4, 8}
  *   chunk_symbols C >= 1; the chunk must fit in on-chip memory
- *                 (C * S <= 60 KiB), else GPULZ_ERR_UNSUPPORTED
+ *                 (C * S <= 48 KiB), else GPULZ_ERR_UNSUPPORTED
  *   window        W in [1, 256]
  *   min_match     in [1, 255]
  *   out_capacity  bytes available at d_out

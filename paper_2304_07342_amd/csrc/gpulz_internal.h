@@ -9,8 +9,9 @@ namespace gpulz {
 constexpr uint32_t kHeaderBytes = 64;
 constexpr uint32_t kMaxMatch = 255;
 constexpr uint32_t kMaxWindow = 256;
-// Largest chunk (in bytes) the encoder stages in LDS.
-constexpr uint32_t kMaxChunkBytes = 60 * 1024;
+// Largest chunk (C * S bytes) the encoder stages in LDS; with the window pad
+// and the hit bitmap this stays under 64 KiB of LDS per workgroup.
+constexpr uint32_t kMaxChunkBytes = 48 * 1024;
 // Per-wave LDS ring the decoder rebuilds symbols in (independent of C).
 constexpr uint32_t kDecodeRingBytes = 16 * 1024;
 

@@ -77,7 +77,7 @@ FAKE = 1 << 40
     (2, 64, 257, 2, gpulz.GPULZ_ERR_INVALID_ARG),
     (2, 64, 16, 0, gpulz.GPULZ_ERR_INVALID_ARG),
     (2, 64, 16, 256, gpulz.GPULZ_ERR_INVALID_ARG),
-    (8, 8000, 16, 2, gpulz.GPULZ_ERR_UNSUPPORTED),  # 64000 B chunk > LDS budget
+    (8, 6145, 16, 2, gpulz.GPULZ_ERR_UNSUPPORTED),  # 49160 B chunk > LDS budget
 ])
 def test_compress_rejects_bad_parameters(S, C, W, MIN, code):
     st = gpulz.gpulz_compress(FAKE, 4096, S, C, W, MIN, FAKE, 1 << 20, FAKE, FAKE, FAKE, 1 << 30)

@@ -72,7 +72,7 @@ def test_runs_and_caps(S, W):
 
 @pytest.mark.parametrize("S", [1, 2, 4, 8])
 def test_largest_chunk(S):
-    C = 60 * 1024 // S
+    C = 48 * 1024 // S
     x = synth.mixed(3 * C * S + 7, S, seed=S)
     _say("largest chunk", S, C)
     st, s, _, _ = gpu_compress(x, S, C, 256, 2)
