@@ -58,6 +58,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-mib", type=int, default=128)
     ap.add_argument("--skip-decompress", action="store_true")
+    ap.add_argument("--profile-copy", action="store_true",
+                    help="end with one untimed device copy of the input (a known-size "
+                         "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only; multi-GPU runs are not part of this build",
@@ -163,6 +166,10 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(x, S, C, W, MIN, args.cpu_sample_mib << 20)
+    if args.profile_copy:
+        ref = torch.empty_like(d_in)
+        ref.copy_(d_in)
+        torch.cuda.synchronize()
     print(json.dumps(result), flush=True)
 
 
