@@ -23,6 +23,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+
+# HBM bytes per encode launch on this workload from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+# same counter reads for a device copy of the 256 MiB input (FETCH_SIZE reads
+# half the copied bytes: factor 2.0; WRITE_SIZE reads them exactly: 1.0).
+# Valid only for the encoder sources they were taken on (sha256 below).
+ENCODE_COUNTERS = {
+    "sources_sha256": "6ad5150650bd3a23f522b3456a6dc6961db0233f12e8f0545b64b3fe7c9f8f48",
+    "fetch_kib": 131136.0, "fetch_scale": 2.0,
+    "write_kib": 271756.25, "write_scale": 1.0,
+}
+ENCODE_SOURCES = ("paper_2304_07342_amd/csrc/lz_encode.hip", "paper_2304_07342_amd/csrc/wave.h",
+                  "paper_2304_07342_amd/csrc/gpulz_internal.h")
+
+
+def encode_traffic_bytes():
+    """Counter-derived HBM bytes per encode launch, or None if the encoder
+    has changed since the counters were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ENCODE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    c = ENCODE_COUNTERS
+    if h.hexdigest() != c["sources_sha256"]:
+        return None
+    return int((c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024)
 # 256 CUs x 64 lanes x 2.4 GHz: one 32-bit compare per lane per clock.
 ALU_PEAK_TCMP = 256 * 64 * 2.4e9 / 1e12
 
@@ -161,7 +188,8 @@ def main():
         "roofline": {"bound": "alu", "kernel": "encode_kernel<4,4> (match search + parse + encode)",
                      "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TCMP, 3),
                      "unit": "Tcmp/s", "frac": round(achieved / ALU_PEAK_TCMP, 4),
-                     "traffic": None, "compares_per_launch": compares},
+                     "traffic": encode_traffic_bytes(), "compares_per_launch": compares,
+                     "hbm_algorithmic_bytes_per_launch": n + size},
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
