@@ -120,6 +120,8 @@ __device__ __forceinline__ void hit_step(const typename SymType<S>::T (&x)[16 / 
         acc[i] |= ballot(x[i] == q[i + V - j]);
       }
     }
+    // keep at most V compare masks live (more would spill SGPRs)
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
