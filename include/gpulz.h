@@ -131,11 +131,79 @@ gpulz_status gpulz_decompress(const void* d_in, uint64_t in_bytes, void* d_out,
                               uint64_t out_capacity, uint64_t* d_out_bytes, int32_t* d_status,
                               void* d_workspace, size_t ws_bytes, hipStream_t stream);
 
+/* ---- batches ------------------------------------------------------------
+ * Many buffers, each with its own size and symbol width, compressed or
+ * decompressed by one fixed sequence of launches on one stream (a plan
+ * kernel, one persistent kernel that takes (buffer, chunk) work items from a
+ * device-side ticket, a per-buffer scan, a compaction), with no host round
+ * trip and no allocation, so the call can be captured in a HIP graph and
+ * replayed with new array contents. Each buffer's output is a standalone
+ * stream, byte-identical to gpulz_compress / gpulz_decompress on that buffer
+ * with the same parameters.
+ * All arrays below are device memory holding one entry per buffer.
+ */
+
+/* Parameters for one symbol width; zero fields take the library default for
+ * that width. waves_per_chunk is the workgroup size of the chunk encoder in
+ * wavefronts (1, 2 or 4); one batch launch uses the largest value given. */
+typedef struct {
+  uint32_t chunk_symbols;
+  uint32_t window;
+  uint32_t min_match;
+  uint32_t waves_per_chunk;
+} gpulz_params;
+
+/* Current defaults for symbol width S (1, 2, 4 or 8). Host-only. */
+gpulz_status gpulz_default_params(uint32_t symbol_bytes, gpulz_params* params);
+
+/* Replace the defaults for width S (e.g. with an autotuner's choice). Every
+ * field must be valid (no zeros). Host-only; process-wide. */
+gpulz_status gpulz_set_default_params(uint32_t symbol_bytes, const gpulz_params* params);
+
+/* Workspace for gpulz_compress_batch of up to nbufs buffers holding up to
+ * max_total_in_bytes input bytes in total. params_by_width[i] applies to
+ * symbol width 1 << i; NULL means all defaults. Host-only. */
+gpulz_status gpulz_compress_batch_workspace_size(uint64_t nbufs, uint64_t max_total_in_bytes,
+                                                 const gpulz_params params_by_width[4],
+                                                 size_t* ws_bytes);
+
+/* Compress buffer b = d_in_ptrs[b][0 .. d_in_bytes[b]) with symbol width
+ * d_symbol_bytes[b] into d_out_ptrs[b] (capacity d_out_caps[b]). Per buffer,
+ * on the stream: d_out_bytes[b] = its stream size, d_status[b] = GPULZ_OK,
+ * GPULZ_ERR_OUT_OF_SPACE (nothing written to that output),
+ * GPULZ_ERR_INVALID_ARG (bad width, or a pointer not 16-byte aligned) or
+ * GPULZ_ERR_WORKSPACE (the inputs exceed max_total_in_bytes; then every
+ * buffer gets it). Host-detectable errors are returned. */
+gpulz_status gpulz_compress_batch(uint64_t nbufs, const void* const* d_in_ptrs,
+                                  const uint64_t* d_in_bytes, const uint8_t* d_symbol_bytes,
+                                  const gpulz_params params_by_width[4], void* const* d_out_ptrs,
+                                  const uint64_t* d_out_caps, uint64_t* d_out_bytes,
+                                  int32_t* d_status, uint64_t max_total_in_bytes, void* d_workspace,
+                                  size_t ws_bytes, hipStream_t stream);
+
+/* Workspace for gpulz_decompress_batch of up to nbufs streams holding up to
+ * max_total_in_bytes stream bytes in total. Host-only. */
+gpulz_status gpulz_decompress_batch_workspace_size(uint64_t nbufs, uint64_t max_total_in_bytes,
+                                                   size_t* ws_bytes);
+
+/* Decompress stream b = d_in_ptrs[b][0 .. d_in_bytes[b]) into d_out_ptrs[b]
+ * (capacity d_out_caps[b]). Per buffer, on the stream: d_out_bytes[b] = its
+ * original size (0 if the header is invalid), d_status[b] = GPULZ_OK,
+ * GPULZ_ERR_CORRUPT, GPULZ_ERR_OUT_OF_SPACE, GPULZ_ERR_INVALID_ARG (a pointer
+ * not 16-byte aligned) or GPULZ_ERR_WORKSPACE (the streams exceed
+ * max_total_in_bytes). */
+gpulz_status gpulz_decompress_batch(uint64_t nbufs, const void* const* d_in_ptrs,
+                                    const uint64_t* d_in_bytes, void* const* d_out_ptrs,
+                                    const uint64_t* d_out_caps, uint64_t* d_out_bytes,
+                                    int32_t* d_status, uint64_t max_total_in_bytes,
+                                    void* d_workspace, size_t ws_bytes, hipStream_t stream);
+
 /* Kernel timing for benchmarks. While enabled, every gpulz_compress and
  * gpulz_decompress call records a pair of HIP events on its own stream
  * around each kernel it launches, so the times cover exactly those kernels.
  * Kernel ids: 0 chunk encode, 1 global scan + header, 2 record scatter,
- * 3 decode prepare (header check + table scan), 4 chunk decode.
+ * 3 decode prepare (header check + table scan), 4 chunk decode, 5 a whole
+ * gpulz_compress_batch call, 6 a whole gpulz_decompress_batch call.
  * gpulz_profile_enable(1) clears the accumulated times, (0) stops recording.
  * gpulz_profile_read waits for the recorded events and writes, for each of
  * the first `nkernels` ids, the summed milliseconds and the launch count

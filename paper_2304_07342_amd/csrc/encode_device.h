@@ -1,0 +1,363 @@
+// Device code of the chunk encoder, shared by the single-buffer kernel and
+// the persistent batch kernel.
+#pragma once
+
+#include "gpulz_internal.h"
+#include "wave.h"
+
+namespace gpulz {
+namespace enc {
+
+// Chunk encoder: one workgroup of wavefronts per chunk.
+//
+// Steps, following gpuLZ (Zhang et al., ICS'23):
+//   stage   the chunk is copied HBM -> LDS with 16-byte loads; window and
+//           look-ahead live in the same LDS array (section 3.3.2, unified
+//           shared buffer).
+//   hits    (all waves) for every position p, whether any offset
+//           d <= min(W, p) has sym[p - d] == sym[p]; a position without such
+//           an offset can only be a literal. Each lane owns a 16-byte vector
+//           of V = 16 / S consecutive positions; one aligned 16-byte window
+//           read per V offsets feeds V x V symbol compares (v_cmp, result in
+//           a 64-bit lane mask), so LDS traffic is one byte per compare.
+//   parse   (wave 0) greedy LZSS (section 2.2 basic steps; section 3.3.2
+//           encoding step): runs of positions without a hit become literals
+//           in bulk; at a hit, the exact longest match is found with the 64
+//           lanes holding window offsets (up to 4 columns of 64): the 64-bit
+//           mask of offsets still matching is ANDed with the comparison at
+//           each next look-ahead symbol, offsets d <= L drop out (a match
+//           never exceeds its offset, section 3.3.2). Rows are computed four
+//           at a time so one LDS round trip serves four extension steps. The
+//           length is the number of steps before the mask empties (at most
+//           255, and never past the chunk end); the offset is the highest
+//           surviving bit, so ties go to the largest offset. Positions
+//           covered by a pointer are never searched.
+//   encode  (wave 0) every 64 tokens, one token per lane: the flag bits are
+//           the ballot of the pointer lanes and each lane's payload offset is
+//           S * (literal lanes below it) + 2 * (pointer lanes below it), via
+//           mbcnt (the local prefix sum of section 3.2.2, over token sizes).
+// The record goes to a per-chunk scratch slot; the chunk's flag and payload
+// sizes go to `sizes` for the global prefix sum.
+
+
+constexpr int kEncodeWaves = 4;
+
+// One chunk's work.
+struct ChunkJob {
+  const uint8_t* src;   // first input byte of the chunk
+  uint64_t src_avail;   // input bytes readable from src (bounds the 16-byte loads)
+  uint32_t c;           // symbols in this chunk
+  uint32_t C;           // nominal chunk symbols (LDS layout)
+  uint32_t W, MIN;
+  uint8_t* slot;        // scratch record: [flag area | payload]
+  uint64_t flag_area;
+  uint32_t* sizes;      // receives {F, P}
+};
+
+
+template <int S> struct Geo {
+  static constexpr int V = 16 / S;                  // symbols per 16-byte vector
+  static constexpr uint32_t kBlock = 64u * V;       // positions per wave block
+};
+
+// LDS layout: [pad | chunk (rounded up to whole 1 KiB blocks) + slack | hit bitmap]
+template <int S, int WC>
+__host__ __device__ constexpr uint32_t pad_bytes() {
+  return (uint32_t)align_up(64u * WC * S + 16u, 16);
+}
+__host__ __device__ constexpr uint64_t chunk_lds_bytes(uint32_t C, uint32_t S) {
+  return align_up((uint64_t)C * S, 1024) + 64;
+}
+__host__ __device__ constexpr uint64_t hit_words(uint32_t C, uint32_t S) {
+  return align_up(C, 1024 / S) / 32 + 64;
+}
+
+template <int S>
+__device__ __forceinline__ typename SymType<S>::T vec_elem(const uint4& v, int e) {
+  using T = typename SymType<S>::T;
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  if constexpr (S == 8) {
+    return (T)w[2 * e] | ((T)w[2 * e + 1] << 32);
+  } else if constexpr (S == 4) {
+    return (T)w[e];
+  } else if constexpr (S == 2) {
+    return (T)(w[e >> 1] >> (16 * (e & 1)));
+  } else {
+    return (T)(w[e >> 2] >> (8 * (e & 3)));
+  }
+}
+
+// Token descriptors: bit 0 = pointer; literal: bits 1.. = chunk position;
+// pointer: bits 1..8 = length, bits 9..16 = offset & 0xFF.
+template <int S>
+__device__ __forceinline__ void encode_group(uint32_t cnt, uint32_t desc, uint32_t group,
+                                             const typename SymType<S>::T* win, uint8_t* slot,
+                                             uint64_t flag_area, uint32_t& pay) {
+  using T = typename SymType<S>::T;
+  const uint32_t lane = lane_id();
+  const bool valid = lane < cnt;
+  const bool is_ptr = valid && (desc & 1u);
+  const uint64_t pm = ballot(is_ptr);
+  const uint64_t lm = ballot(valid && !(desc & 1u));
+  const uint32_t off = pay + S * mbcnt(lm) + 2u * mbcnt(pm);
+  uint8_t* dst = slot + flag_area + off;
+  if (is_ptr) {
+    dst[0] = (uint8_t)(desc >> 1);
+    dst[1] = (uint8_t)(desc >> 9);
+  } else if (valid) {
+    T v = win[desc >> 1];
+#pragma unroll
+    for (int b = 0; b < S; ++b) dst[b] = (uint8_t)((uint64_t)v >> (8 * b));
+  }
+  if (lane == 0) *reinterpret_cast<uint64_t*>(slot + 8u * group) = pm;
+  pay += S * popc64(lm) + 2u * popc64(pm);
+}
+
+// Compares this lane's V symbols x[] with the window vector q (the V symbols
+// that sit V * k positions back) and the vector after it (prev), for the
+// offsets d = V * (k - 1) + j, j = 1 .. jmax.
+template <int S, bool kHead, bool kPartial>
+__device__ __forceinline__ void hit_step(const typename SymType<S>::T (&x)[16 / S],
+                                         const uint4& qv, const uint4& prev, uint32_t dk,
+                                         uint32_t jmax, uint32_t pos0, uint64_t (&acc)[16 / S]) {
+  using T = typename SymType<S>::T;
+  constexpr int V = Geo<S>::V;
+  T q[2 * V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    q[e] = vec_elem<S>(qv, e);
+    q[V + e] = vec_elem<S>(prev, e);
+  }
+#pragma unroll
+  for (int j = 1; j <= V; ++j) {
+    if (kPartial && (uint32_t)j > jmax) break;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      if constexpr (kHead) {
+        acc[i] |= ballot((x[i] == q[i + V - j]) & (pos0 + i >= dk + j));
+      } else {
+        acc[i] |= ballot(x[i] == q[i + V - j]);
+      }
+    }
+    // keep at most V compare masks live (more would spill SGPRs)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Hit bitmap for one block of 64 * V positions starting at `base`: bit p is
+// set iff some offset d <= min(W, p) has sym[p - d] == sym[p].
+template <int S, bool kHead>
+__device__ __forceinline__ void hit_block(const uint4* w4, uint32_t base, uint32_t W,
+                                          uint32_t* hits) {
+  using T = typename SymType<S>::T;
+  constexpr int V = Geo<S>::V;
+  const uint32_t lane = lane_id();
+  const int vbase = (int)(base / V + lane);
+  const uint4 xv = w4[vbase];
+  T x[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) x[i] = vec_elem<S>(xv, i);
+  uint64_t acc[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) acc[i] = 0;
+  const uint32_t pos0 = base + V * lane;  // this lane's first position
+  const uint32_t kfull = W / V;           // steps whose V offsets are all <= W
+  uint4 prev = xv;
+  uint32_t k = 1;
+  for (; k + 1 <= kfull; k += 2) {
+    const uint4 q1 = w4[vbase - (int)k];
+    const uint4 q2 = w4[vbase - (int)k - 1];
+    hit_step<S, kHead, false>(x, q1, prev, V * (k - 1), V, pos0, acc);
+    hit_step<S, kHead, false>(x, q2, q1, V * k, V, pos0, acc);
+    prev = q2;
+  }
+  if (k <= kfull) {
+    const uint4 q1 = w4[vbase - (int)k];
+    hit_step<S, kHead, false>(x, q1, prev, V * (k - 1), V, pos0, acc);
+    prev = q1;
+    ++k;
+  }
+  if (W % V) {
+    const uint4 q1 = w4[vbase - (int)k];
+    hit_step<S, kHead, true>(x, q1, prev, V * (k - 1), W % V, pos0, acc);
+  }
+  uint32_t bits = 0;
+#pragma unroll
+  for (int i = 0; i < V; ++i) bits |= (uint32_t)((acc[i] >> lane) & 1u) << i;
+  if (bits) atomicOr(&hits[pos0 >> 5], bits << (pos0 & 31u));
+}
+
+// Encodes one chunk into its scratch slot and writes {F, P} to job.sizes.
+// Every wave of the workgroup stages the chunk and builds the hit bitmap;
+// waves other than 0 return after that, wave 0 parses and encodes.
+template <int S, int WC>
+__device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
+  using T = typename SymType<S>::T;
+  constexpr int V = Geo<S>::V;
+  constexpr uint32_t kBlock = Geo<S>::kBlock;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = tid >> 6;
+  const uint32_t nwaves = blockDim.x >> 6;
+  const uint32_t c = job.c;
+  uint8_t* stage = lds + pad_bytes<S, WC>();
+  uint32_t* hits = reinterpret_cast<uint32_t*>(stage + chunk_lds_bytes(job.C, S));
+  const uint32_t nhw = (uint32_t)hit_words(job.C, S);
+
+  // ---- stage: HBM -> LDS with 16-byte loads; the chunk lands 16-byte
+  // aligned in LDS whatever its alignment in HBM.
+  {
+    const uint32_t nbytes = c * S;
+    if (((uintptr_t)job.src & 15) == 0) {
+      const uint32_t nw = (nbytes + 15) / 16;
+      for (uint32_t k = tid; k < nw; k += blockDim.x) {
+        const uint64_t g = 16ull * k;
+        if (g + 16 <= job.src_avail) {
+          *reinterpret_cast<uint4*>(stage + 16 * k) = *reinterpret_cast<const uint4*>(job.src + g);
+        } else {
+          for (uint32_t b = 0; b < 16; ++b) stage[16 * k + b] = g + b < job.src_avail ? job.src[g + b] : 0;
+        }
+      }
+    } else {
+      for (uint32_t k = tid; k < nbytes; k += blockDim.x) stage[k] = job.src[k];
+    }
+    for (uint32_t k = tid; k < nhw; k += blockDim.x) hits[k] = 0;
+  }
+  __syncthreads();
+
+  // ---- hits: all waves, one block of 64 * V positions at a time
+  {
+    const uint4* w4 = reinterpret_cast<const uint4*>(stage);
+    const uint32_t nblocks = (c + kBlock - 1) / kBlock;
+    for (uint32_t b = wave; b < nblocks; b += nwaves) {
+      const uint32_t base = b * kBlock;
+      if (base >= job.W) {
+        hit_block<S, false>(w4, base, job.W, hits);
+      } else {
+        hit_block<S, true>(w4, base, job.W, hits);
+      }
+    }
+  }
+  __syncthreads();
+  if (wave != 0) return;
+
+  // ---- parse + encode: wave 0
+  const T* win = reinterpret_cast<const T*>(stage);
+  uint64_t wmask[WC];
+#pragma unroll
+  for (int col = 0; col < WC; ++col) wmask[col] = ballot(64u * col + lane + 1u <= job.W);
+
+  uint8_t* slot = job.slot;
+  uint32_t ntok = 0, pay = 0, desc = 0;
+  uint32_t p = 0;
+  // 64 consecutive bitmap words cached one per lane
+  uint32_t hw0 = 0;
+  uint32_t hcache = hits[lane];
+  while (p < c) {
+    // next hit at or after p
+    uint32_t h = c;
+    {
+      const uint32_t pw = p >> 5;  // bitmap word holding position p
+      uint32_t w = pw;
+      uint32_t first_bits = 0;
+      for (;;) {
+        if (w >= hw0 + 64) {
+          hw0 = w;
+          hcache = hw0 + lane < nhw ? hits[hw0 + lane] : 0u;
+        }
+        uint32_t mine = hcache;
+        const uint32_t gw = hw0 + lane;
+        if (gw < pw) mine = 0;
+        else if (gw == pw) mine &= ~0u << (p & 31u);
+        const uint64_t nz = ballot(mine != 0);
+        if (nz) {
+          const uint32_t l = (uint32_t)__ffsll((unsigned long long)nz) - 1;
+          first_bits = readlane(mine, l);
+          h = min(c, (hw0 + l) * 32u + (uint32_t)__ffs(first_bits) - 1u);
+          break;
+        }
+        w = hw0 + 64;
+        if (w * 32u >= c) break;
+      }
+    }
+    // literals for [p, h)
+    while (p < h) {
+      const uint32_t sl = ntok & 63u;
+      const uint32_t take = min(h - p, 64u - sl);
+      if (lane >= sl && lane < sl + take) desc = (p + lane - sl) << 1;
+      ntok += take;
+      p += take;
+      if ((ntok & 63u) == 0) encode_group<S>(64, desc, (ntok >> 6) - 1, win, slot, job.flag_area, pay);
+    }
+    if (h >= c) break;
+
+    // exact longest match at h
+    uint64_t A[WC];
+#pragma unroll
+    for (int col = 0; col < WC; ++col) A[col] = wmask[col] & ballot(64u * col + lane + 1u <= h);
+    uint32_t L = 0;
+    const uint32_t lim = min(kMaxMatch, c - h);
+    bool alive = true;
+    while (alive && L < lim) {
+      uint64_t R[4][WC];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t q = min(h + L + r, c - 1);
+        const T xq = win[q];
+#pragma unroll
+        for (int col = 0; col < WC; ++col) {
+          const uint32_t d = 64u * col + lane + 1u;
+          R[r][col] = ballot((win[(int)q - (int)d] == xq) & (d > L + r));
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (alive && L < lim) {
+          uint64_t any = 0;
+          uint64_t B[WC];
+#pragma unroll
+          for (int col = 0; col < WC; ++col) {
+            B[col] = A[col] & R[r][col];
+            any |= B[col];
+          }
+          if (any) {
+#pragma unroll
+            for (int col = 0; col < WC; ++col) A[col] = B[col];
+            ++L;
+          } else {
+            alive = false;
+          }
+        }
+      }
+    }
+    uint32_t val;
+    if (L >= job.MIN) {
+      uint32_t d = 0;
+#pragma unroll
+      for (int col = WC - 1; col >= 0; --col) {
+        if (d == 0 && A[col]) d = 64u * col + 64u - (uint32_t)__clzll(A[col]);
+      }
+      val = 1u | (L << 1) | ((d & 0xFFu) << 9);
+      p = h + L;
+    } else {
+      val = h << 1;
+      p = h + 1;
+    }
+    if (lane == (ntok & 63u)) desc = val;
+    ++ntok;
+    if ((ntok & 63u) == 0) encode_group<S>(64, desc, (ntok >> 6) - 1, win, slot, job.flag_area, pay);
+  }
+  if (ntok & 63u) encode_group<S>(ntok & 63u, desc, ntok >> 6, win, slot, job.flag_area, pay);
+  if (lane == 0) {
+    job.sizes[0] = (ntok + 7) / 8;
+    job.sizes[1] = pay;
+  }
+}
+
+template <int S, int WC>
+__host__ __device__ constexpr size_t lds_bytes(uint32_t C) {
+  return pad_bytes<S, WC>() + chunk_lds_bytes(C, S) + 4 * hit_words(C, S);
+}
+
+}  // namespace enc
+}  // namespace gpulz

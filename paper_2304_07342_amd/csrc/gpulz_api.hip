@@ -13,7 +13,7 @@ using namespace gpulz;
 namespace {
 
 // ---- optional per-kernel event timing ---------------------------------------
-constexpr int kProfKernels = 5;
+constexpr int kProfKernels = 7;
 struct EventPair {
   int kernel;
   hipEvent_t start, stop;
@@ -52,6 +52,83 @@ bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0;
 uint64_t num_chunks(uint64_t nbytes, uint32_t S, uint32_t C) {
   const uint64_t m = nbytes / S;
   return (m + C - 1) / C;
+}
+
+// ---- per-width defaults and batch layouts ------------------------------------
+
+std::mutex g_defaults_mu;
+gpulz_params g_defaults[4] = {
+    {4096, 128, 2, 4},  // S = 1
+    {2048, 128, 2, 4},  // S = 2
+    {4096, 256, 2, 4},  // S = 4
+    {2048, 256, 2, 4},  // S = 8
+};
+
+int width_index(uint32_t S) { return S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : S == 8 ? 3 : -1; }
+
+bool valid_waves(uint32_t w) { return w == 1 || w == 2 || w == 4; }
+
+// Fills zero fields from the defaults and checks the result.
+bool resolve_params(const gpulz_params* in, WidthParams& wp, uint32_t& waves, size_t& lds) {
+  std::lock_guard<std::mutex> lk(g_defaults_mu);
+  waves = 0;
+  lds = 0;
+  for (int w = 0; w < 4; ++w) {
+    const uint32_t S = 1u << w;
+    gpulz_params p = in ? in[w] : gpulz_params{0, 0, 0, 0};
+    if (p.chunk_symbols == 0) p.chunk_symbols = g_defaults[w].chunk_symbols;
+    if (p.window == 0) p.window = g_defaults[w].window;
+    if (p.min_match == 0) p.min_match = g_defaults[w].min_match;
+    if (p.waves_per_chunk == 0) p.waves_per_chunk = g_defaults[w].waves_per_chunk;
+    if (!valid_params(S, p.chunk_symbols, p.window, p.min_match) || !valid_waves(p.waves_per_chunk))
+      return false;
+    if ((uint64_t)p.chunk_symbols * S > kMaxChunkBytes) return false;
+    wp.C[w] = p.chunk_symbols;
+    wp.W[w] = p.window;
+    wp.MIN[w] = p.min_match;
+    const SlotLayout sl = slot_layout(p.chunk_symbols, S, p.min_match);
+    wp.slot_bytes[w] = sl.slot_bytes;
+    wp.flag_area[w] = sl.flag_area;
+    waves = waves > p.waves_per_chunk ? waves : p.waves_per_chunk;
+    const size_t l = encode_lds_bytes(p.chunk_symbols, S, p.window);
+    lds = lds > l ? lds : l;
+  }
+  return true;
+}
+
+BatchEncLayout batch_enc_layout(uint64_t nbufs, uint64_t max_total, const WidthParams& wp) {
+  uint64_t min_sc = ~0ull, max_slot = 0;
+  double max_ratio = 0;
+  for (int w = 0; w < 4; ++w) {
+    const uint64_t sc = (uint64_t)wp.C[w] << w;
+    min_sc = sc < min_sc ? sc : min_sc;
+    max_slot = wp.slot_bytes[w] > max_slot ? wp.slot_bytes[w] : max_slot;
+    const double r = (double)wp.slot_bytes[w] / (double)sc;
+    max_ratio = r > max_ratio ? r : max_ratio;
+  }
+  BatchEncLayout l;
+  l.max_chunks = max_total / min_sc + nbufs;
+  l.slot_cap = (uint64_t)((double)max_total * max_ratio) + nbufs * max_slot + 4096;
+  l.ctrl_off = 0;
+  l.bufs_off = 256;
+  l.sizes_off = l.bufs_off + align_up(nbufs * sizeof(BatchEncBuf), 256);
+  l.offs_off = l.sizes_off + align_up(8 * l.max_chunks, 256);
+  l.slots_off = l.offs_off + align_up(8 * l.max_chunks, 256);
+  l.total = l.slots_off + align_up(l.slot_cap, 256) + 256;
+  return l;
+}
+
+struct BatchDecLayout {
+  uint64_t bufs_off, groups_off, total, group_cap;
+};
+
+BatchDecLayout batch_dec_layout(uint64_t nbufs, uint64_t max_total) {
+  BatchDecLayout l;
+  l.group_cap = max_total / 640 + 2 * nbufs + 16;
+  l.bufs_off = 256;
+  l.groups_off = l.bufs_off + align_up(nbufs * sizeof(BatchDecBuf), 256);
+  l.total = l.groups_off + align_up(8 * l.group_cap, 256);
+  return l;
 }
 
 }  // namespace
@@ -174,7 +251,7 @@ gpulz_status gpulz_peek_header(const void* h_header, size_t header_bytes, uint64
 
 gpulz_status gpulz_decompress_workspace_size(uint64_t stream_bytes, size_t* ws_bytes) {
   if (!ws_bytes) return GPULZ_ERR_INVALID_ARG;
-  *ws_bytes = (size_t)(256 + 8 * (decode_max_chunks(stream_bytes) + 1));
+  *ws_bytes = (size_t)(256 + 8 * decode_group_slots(stream_bytes));
   return GPULZ_OK;
 }
 
@@ -192,15 +269,14 @@ gpulz_status gpulz_decompress(const void* d_in, uint64_t in_bytes, void* d_out, 
   pa.in = static_cast<const uint8_t*>(d_in);
   pa.in_bytes = in_bytes;
   pa.capacity = out_capacity;
-  pa.max_chunks = decode_max_chunks(in_bytes);
   pa.params = reinterpret_cast<DecodeParams*>(ws);
-  pa.offsets = reinterpret_cast<uint64_t*>(ws + 256);
+  pa.group_off = reinterpret_cast<uint64_t*>(ws + 256);
   pa.out_bytes = d_out_bytes;
   pa.status = d_status;
   DecodeArgs da;
   da.in = pa.in;
   da.params = pa.params;
-  da.offsets = pa.offsets;
+  da.group_off = pa.group_off;
   da.out = static_cast<uint8_t*>(d_out);
   da.status = d_status;
   int pi = prof_begin(3, stream);
@@ -208,6 +284,118 @@ gpulz_status gpulz_decompress(const void* d_in, uint64_t in_bytes, void* d_out, 
   prof_end(pi, stream);
   pi = prof_begin(4, stream);
   if (launch_decode_chunks(da, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  prof_end(pi, stream);
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_default_params(uint32_t S, gpulz_params* params) {
+  const int w = width_index(S);
+  if (w < 0 || !params) return GPULZ_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_defaults_mu);
+  *params = g_defaults[w];
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_set_default_params(uint32_t S, const gpulz_params* params) {
+  const int w = width_index(S);
+  if (w < 0 || !params) return GPULZ_ERR_INVALID_ARG;
+  const gpulz_params& p = *params;
+  if (!valid_params(S, p.chunk_symbols, p.window, p.min_match) || !valid_waves(p.waves_per_chunk) ||
+      (uint64_t)p.chunk_symbols * S > kMaxChunkBytes)
+    return GPULZ_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_defaults_mu);
+  g_defaults[w] = p;
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_compress_batch_workspace_size(uint64_t nbufs, uint64_t max_total_in_bytes,
+                                                 const gpulz_params params_by_width[4],
+                                                 size_t* ws_bytes) {
+  WidthParams wp;
+  uint32_t waves;
+  size_t lds;
+  if (!ws_bytes || !resolve_params(params_by_width, wp, waves, lds)) return GPULZ_ERR_INVALID_ARG;
+  *ws_bytes = (size_t)batch_enc_layout(nbufs, max_total_in_bytes, wp).total;
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_compress_batch(uint64_t nbufs, const void* const* d_in_ptrs,
+                                  const uint64_t* d_in_bytes, const uint8_t* d_symbol_bytes,
+                                  const gpulz_params params_by_width[4], void* const* d_out_ptrs,
+                                  const uint64_t* d_out_caps, uint64_t* d_out_bytes,
+                                  int32_t* d_status, uint64_t max_total_in_bytes, void* d_ws,
+                                  size_t ws_bytes, hipStream_t stream) {
+  if (nbufs == 0) return GPULZ_OK;
+  if (!d_in_ptrs || !d_in_bytes || !d_symbol_bytes || !d_out_ptrs || !d_out_caps || !d_out_bytes ||
+      !d_status || nbufs > 0xFFFFFFFFull)
+    return GPULZ_ERR_INVALID_ARG;
+  WidthParams wp;
+  uint32_t waves;
+  size_t lds;
+  if (!resolve_params(params_by_width, wp, waves, lds)) return GPULZ_ERR_INVALID_ARG;
+  if (!aligned(d_ws, 256)) return GPULZ_ERR_INVALID_ARG;
+  const BatchEncLayout l = batch_enc_layout(nbufs, max_total_in_bytes, wp);
+  if (!d_ws || ws_bytes < l.total) return GPULZ_ERR_WORKSPACE;
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  BatchEncArgs a;
+  a.nbufs = nbufs;
+  a.in_ptrs = d_in_ptrs;
+  a.in_bytes = d_in_bytes;
+  a.symbol_bytes = d_symbol_bytes;
+  a.out_ptrs = d_out_ptrs;
+  a.out_caps = d_out_caps;
+  a.out_bytes = d_out_bytes;
+  a.status = d_status;
+  a.max_total_in_bytes = max_total_in_bytes;
+  a.wp = wp;
+  a.ctrl = reinterpret_cast<BatchCtrl*>(ws + l.ctrl_off);
+  a.bufs = reinterpret_cast<BatchEncBuf*>(ws + l.bufs_off);
+  a.sizes = reinterpret_cast<uint32_t*>(ws + l.sizes_off);
+  a.offs = reinterpret_cast<uint64_t*>(ws + l.offs_off);
+  a.slots = ws + l.slots_off;
+  a.max_chunks = l.max_chunks;
+  a.slot_cap = l.slot_cap;
+  int pi = prof_begin(5, stream);
+  if (launch_compress_batch(a, waves, lds, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  prof_end(pi, stream);
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_decompress_batch_workspace_size(uint64_t nbufs, uint64_t max_total_in_bytes,
+                                                   size_t* ws_bytes) {
+  if (!ws_bytes) return GPULZ_ERR_INVALID_ARG;
+  *ws_bytes = (size_t)batch_dec_layout(nbufs, max_total_in_bytes).total;
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_decompress_batch(uint64_t nbufs, const void* const* d_in_ptrs,
+                                    const uint64_t* d_in_bytes, void* const* d_out_ptrs,
+                                    const uint64_t* d_out_caps, uint64_t* d_out_bytes,
+                                    int32_t* d_status, uint64_t max_total_in_bytes, void* d_ws,
+                                    size_t ws_bytes, hipStream_t stream) {
+  if (nbufs == 0) return GPULZ_OK;
+  if (!d_in_ptrs || !d_in_bytes || !d_out_ptrs || !d_out_caps || !d_out_bytes || !d_status ||
+      nbufs > 0xFFFFFFFFull)
+    return GPULZ_ERR_INVALID_ARG;
+  if (!aligned(d_ws, 256)) return GPULZ_ERR_INVALID_ARG;
+  const BatchDecLayout l = batch_dec_layout(nbufs, max_total_in_bytes);
+  if (!d_ws || ws_bytes < l.total) return GPULZ_ERR_WORKSPACE;
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  BatchDecArgs a;
+  a.nbufs = nbufs;
+  a.in_ptrs = d_in_ptrs;
+  a.in_bytes = d_in_bytes;
+  a.out_ptrs = d_out_ptrs;
+  a.out_caps = d_out_caps;
+  a.out_bytes = d_out_bytes;
+  a.status = d_status;
+  a.max_total_in_bytes = max_total_in_bytes;
+  a.ctrl = reinterpret_cast<BatchCtrl*>(ws);
+  a.bufs = reinterpret_cast<BatchDecBuf*>(ws + l.bufs_off);
+  a.group_off = reinterpret_cast<uint64_t*>(ws + l.groups_off);
+  a.group_cap = l.group_cap;
+  int pi = prof_begin(6, stream);
+  if (launch_decompress_batch(a, stream) != hipSuccess) return GPULZ_ERR_HIP;
   prof_end(pi, stream);
   return GPULZ_OK;
 }

@@ -16,7 +16,7 @@ constexpr uint32_t kMaxChunkBytes = 48 * 1024;
 constexpr uint32_t kDecodeRingBytes = 16 * 1024;
 
 // Device status values (same numbering as gpulz_status).
-enum : int32_t { kOk = 0, kOutOfSpace = 2, kCorrupt = 3 };
+enum : int32_t { kOk = 0, kInvalidArg = 1, kOutOfSpace = 2, kCorrupt = 3, kWorkspace = 4 };
 
 __host__ __device__ constexpr uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
@@ -100,19 +100,25 @@ struct DecodeParams {
   uint64_t n, m, N;
 };
 
-// Workspace = DecodeParams (256 B) | record offsets[max_chunks + 1] (u64).
+// Upper bound on the chunks of a valid stream: every chunk costs at least 8
+// table bytes, 1 flag byte and 1 payload byte.
 __host__ __device__ inline uint64_t decode_max_chunks(uint64_t stream_bytes) {
-  // every chunk costs at least 8 table bytes, 1 flag byte and 1 payload byte
   return stream_bytes > kHeaderBytes ? (stream_bytes - kHeaderBytes) / 10 : 0;
 }
 
+// Record offsets are kept for every 64th chunk (a chunk's own offset is its
+// group's plus a wave prefix sum over the group's table entries).
+__host__ __device__ inline uint64_t decode_group_slots(uint64_t stream_bytes) {
+  return (decode_max_chunks(stream_bytes) + 63) / 64 + 1;
+}
+
+// Workspace = DecodeParams (256 B) | group offsets[decode_group_slots] (u64).
 struct DecodePrepArgs {
   const uint8_t* in;
   uint64_t in_bytes;
   uint64_t capacity;
-  uint64_t max_chunks;
   DecodeParams* params;
-  uint64_t* offsets;
+  uint64_t* group_off;
   uint64_t* out_bytes;
   int32_t* status;
 };
@@ -120,12 +126,87 @@ struct DecodePrepArgs {
 struct DecodeArgs {
   const uint8_t* in;
   const DecodeParams* params;
-  const uint64_t* offsets;
+  const uint64_t* group_off;
   uint8_t* out;
   int32_t* status;
 };
 
 hipError_t launch_decode_prepare(const DecodePrepArgs& a, hipStream_t s);
 hipError_t launch_decode_chunks(const DecodeArgs& a, hipStream_t s);
+
+// ---- batches ----------------------------------------------------------------
+
+// Per-width parameters as the kernels see them (index = log2 S).
+struct WidthParams {
+  uint32_t C[4], W[4], MIN[4];
+  uint64_t slot_bytes[4], flag_area[4];
+};
+
+struct BatchCtrl {
+  uint64_t ticket;      // next work item of the persistent kernel
+  uint64_t T;           // work items (chunks) in the batch
+  uint64_t slot_total;  // scratch slot bytes used
+};
+
+struct BatchEncBuf {
+  uint64_t chunk_base;  // first work item of this buffer
+  uint64_t slot_base;   // its first scratch slot (bytes into the slot region)
+  uint64_t n;           // input bytes
+  uint64_t N;           // chunks
+  uint32_t S, C, W, MIN;
+  uint32_t slot_bytes, flag_area;
+  int32_t status;
+  uint32_t pad;
+};
+
+struct BatchEncLayout {
+  uint64_t ctrl_off, bufs_off, sizes_off, offs_off, slots_off, total;
+  uint64_t max_chunks, slot_cap;
+};
+
+struct BatchEncArgs {
+  uint64_t nbufs;
+  const void* const* in_ptrs;
+  const uint64_t* in_bytes;
+  const uint8_t* symbol_bytes;
+  void* const* out_ptrs;
+  const uint64_t* out_caps;
+  uint64_t* out_bytes;
+  int32_t* status;
+  uint64_t max_total_in_bytes;
+  WidthParams wp;
+  BatchCtrl* ctrl;
+  BatchEncBuf* bufs;
+  uint32_t* sizes;      // 2 per work item
+  uint64_t* offs;       // per work item, offset of its record within its stream's records
+  uint8_t* slots;
+  uint64_t max_chunks, slot_cap;
+};
+
+struct BatchDecBuf {
+  DecodeParams p;
+  uint64_t chunk_base;  // first work item of this buffer
+  uint64_t group_base;  // first record-offset group slot
+  uint64_t groups;      // group slots used (ceil(N / 64) + 1), 0 if the header is bad
+};
+
+struct BatchDecArgs {
+  uint64_t nbufs;
+  const void* const* in_ptrs;
+  const uint64_t* in_bytes;
+  void* const* out_ptrs;
+  const uint64_t* out_caps;
+  uint64_t* out_bytes;
+  int32_t* status;
+  uint64_t max_total_in_bytes;
+  BatchCtrl* ctrl;
+  BatchDecBuf* bufs;
+  uint64_t* group_off;
+  uint64_t group_cap;
+};
+
+hipError_t launch_compress_batch(const BatchEncArgs& a, uint32_t waves, size_t lds_bytes,
+                                 hipStream_t s);
+hipError_t launch_decompress_batch(const BatchDecArgs& a, hipStream_t s);
 
 }  // namespace gpulz

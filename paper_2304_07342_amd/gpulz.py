@@ -26,10 +26,33 @@ GPULZ_ERR_UNSUPPORTED = 6
 EXPORTS = (
     "gpulz_abi_version", "gpulz_status_string", "gpulz_compress_bound",
     "gpulz_compress_workspace_size", "gpulz_compress", "gpulz_peek_header",
-    "gpulz_decompress_workspace_size", "gpulz_decompress", "gpulz_profile_enable",
+    "gpulz_decompress_workspace_size", "gpulz_decompress", "gpulz_default_params",
+    "gpulz_set_default_params", "gpulz_compress_batch_workspace_size", "gpulz_compress_batch",
+    "gpulz_decompress_batch_workspace_size", "gpulz_decompress_batch", "gpulz_profile_enable",
     "gpulz_profile_read",
 )
-KERNEL_NAMES = ("encode", "scan", "scatter", "decode_prepare", "decode")
+KERNEL_NAMES = ("encode", "scan", "scatter", "decode_prepare", "decode", "compress_batch",
+                "decompress_batch")
+
+
+class Params(ctypes.Structure):
+    """gpulz_params: per-width parameters (zero fields = library default)."""
+    _fields_ = [("chunk_symbols", ctypes.c_uint32), ("window", ctypes.c_uint32),
+                ("min_match", ctypes.c_uint32), ("waves_per_chunk", ctypes.c_uint32)]
+
+
+ParamsArray4 = Params * 4
+
+
+def params_array(by_width=None):
+    """by_width: None, or {S: (chunk, window, min_match[, waves])} for any of
+    S in 1, 2, 4, 8 (others default)."""
+    arr = ParamsArray4()
+    for S, p in (by_width or {}).items():
+        w = {1: 0, 2: 1, 4: 2, 8: 3}[S]
+        p = tuple(p) + (0,) * (4 - len(p))
+        arr[w] = Params(*p)
+    return arr
 
 
 class GpulzError(RuntimeError):
@@ -66,6 +89,20 @@ def lib() -> ctypes.CDLL:
         L.gpulz_decompress_workspace_size.argtypes = [u64, ctypes.POINTER(sz)]
         L.gpulz_decompress.restype = ctypes.c_int
         L.gpulz_decompress.argtypes = [vp, u64, vp, u64, vp, vp, vp, sz, vp]
+        L.gpulz_default_params.restype = ctypes.c_int
+        L.gpulz_default_params.argtypes = [u32, ctypes.POINTER(Params)]
+        L.gpulz_set_default_params.restype = ctypes.c_int
+        L.gpulz_set_default_params.argtypes = [u32, ctypes.POINTER(Params)]
+        L.gpulz_compress_batch_workspace_size.restype = ctypes.c_int
+        L.gpulz_compress_batch_workspace_size.argtypes = [u64, u64, ctypes.POINTER(Params),
+                                                         ctypes.POINTER(sz)]
+        L.gpulz_compress_batch.restype = ctypes.c_int
+        L.gpulz_compress_batch.argtypes = [u64, vp, vp, vp, ctypes.POINTER(Params), vp, vp, vp, vp,
+                                           u64, vp, sz, vp]
+        L.gpulz_decompress_batch_workspace_size.restype = ctypes.c_int
+        L.gpulz_decompress_batch_workspace_size.argtypes = [u64, u64, ctypes.POINTER(sz)]
+        L.gpulz_decompress_batch.restype = ctypes.c_int
+        L.gpulz_decompress_batch.argtypes = [u64, vp, vp, vp, vp, vp, vp, u64, vp, sz, vp]
         L.gpulz_profile_enable.restype = ctypes.c_int
         L.gpulz_profile_enable.argtypes = [ctypes.c_int]
         L.gpulz_profile_read.restype = ctypes.c_int
@@ -128,6 +165,50 @@ def gpulz_decompress(d_in: int, in_bytes: int, d_out: int, out_capacity: int, d_
                      d_status: int, d_workspace: int, ws_bytes: int, stream: int = 0) -> int:
     return lib().gpulz_decompress(d_in, in_bytes, d_out, out_capacity, d_out_bytes, d_status,
                                   d_workspace, ws_bytes, stream)
+
+
+def gpulz_default_params(symbol_bytes: int):
+    p = Params()
+    _check(lib().gpulz_default_params(symbol_bytes, ctypes.byref(p)), "gpulz_default_params")
+    return (p.chunk_symbols, p.window, p.min_match, p.waves_per_chunk)
+
+
+def gpulz_set_default_params(symbol_bytes: int, chunk_symbols: int, window: int, min_match: int,
+                             waves_per_chunk: int = 4) -> None:
+    p = Params(chunk_symbols, window, min_match, waves_per_chunk)
+    _check(lib().gpulz_set_default_params(symbol_bytes, ctypes.byref(p)), "gpulz_set_default_params")
+
+
+def gpulz_compress_batch_workspace_size(nbufs: int, max_total_in_bytes: int, params=None) -> int:
+    ws = ctypes.c_size_t(0)
+    arr = params if isinstance(params, ParamsArray4) else params_array(params)
+    _check(lib().gpulz_compress_batch_workspace_size(nbufs, max_total_in_bytes, arr, ctypes.byref(ws)),
+           "gpulz_compress_batch_workspace_size")
+    return ws.value
+
+
+def gpulz_compress_batch(nbufs, d_in_ptrs, d_in_bytes, d_symbol_bytes, params, d_out_ptrs, d_out_caps,
+                         d_out_bytes, d_status, max_total_in_bytes, d_workspace, ws_bytes,
+                         stream: int = 0) -> int:
+    arr = params if isinstance(params, ParamsArray4) else params_array(params)
+    return lib().gpulz_compress_batch(nbufs, d_in_ptrs, d_in_bytes, d_symbol_bytes, arr, d_out_ptrs,
+                                      d_out_caps, d_out_bytes, d_status, max_total_in_bytes,
+                                      d_workspace, ws_bytes, stream)
+
+
+def gpulz_decompress_batch_workspace_size(nbufs: int, max_total_in_bytes: int) -> int:
+    ws = ctypes.c_size_t(0)
+    _check(lib().gpulz_decompress_batch_workspace_size(nbufs, max_total_in_bytes, ctypes.byref(ws)),
+           "gpulz_decompress_batch_workspace_size")
+    return ws.value
+
+
+def gpulz_decompress_batch(nbufs, d_in_ptrs, d_in_bytes, d_out_ptrs, d_out_caps, d_out_bytes,
+                           d_status, max_total_in_bytes, d_workspace, ws_bytes,
+                           stream: int = 0) -> int:
+    return lib().gpulz_decompress_batch(nbufs, d_in_ptrs, d_in_bytes, d_out_ptrs, d_out_caps,
+                                        d_out_bytes, d_status, max_total_in_bytes, d_workspace,
+                                        ws_bytes, stream)
 
 
 def gpulz_profile_enable(enable: bool) -> None:
@@ -226,3 +307,116 @@ def decompress(s, out_capacity: int | None = None, stream=None, return_status: b
         return status, out[:n] if status == GPULZ_OK else None
     _check(status, "gpulz_decompress (device status)")
     return out[:n]
+
+
+# ---- batches ------------------------------------------------------------------
+
+def _ptr_array(tensors, device):
+    torch = _torch()
+    return torch.tensor([t.data_ptr() for t in tensors], dtype=torch.int64, device=device)
+
+
+class BatchCompressor:
+    """One gpulz_compress_batch call over fixed device buffers.
+
+    inputs: uint8 device tensors (16-byte aligned, as torch allocates);
+    widths: symbol width per buffer; params: {S: (chunk, window, min_match[,
+    waves])} or None. Output buffers are sized by gpulz_compress_bound. The
+    call can be replayed eagerly (`run`) or captured once in a HIP graph
+    (`capture`) and replayed (`replay`); either way the inputs' current
+    contents are compressed."""
+
+    def __init__(self, inputs, widths, params=None, device="cuda"):
+        torch = _torch()
+        self.inputs = list(inputs)
+        self.n = len(self.inputs)
+        self.params = params_array(params)
+        self.sizes = [t.numel() for t in self.inputs]
+        self.widths = list(widths)
+        total = sum(self.sizes)
+        self.max_total = max(total, 1)
+        caps = []
+        for nb, S in zip(self.sizes, self.widths):
+            C, W, MIN, _ = self.resolved(S)
+            caps.append(gpulz_compress_bound(nb, S, C, MIN) if S in (1, 2, 4, 8) else 64)
+        self.outputs = [torch.empty(max(c, 1), dtype=torch.uint8, device=device) for c in caps]
+        self.caps = caps
+        self.d_in_ptrs = _ptr_array(self.inputs, device)
+        self.d_in_bytes = torch.tensor(self.sizes, dtype=torch.int64, device=device)
+        self.d_widths = torch.tensor(self.widths, dtype=torch.uint8, device=device)
+        self.d_out_ptrs = _ptr_array(self.outputs, device)
+        self.d_out_caps = torch.tensor(caps, dtype=torch.int64, device=device)
+        self.d_out_bytes = torch.zeros(self.n, dtype=torch.int64, device=device)
+        self.d_status = torch.zeros(self.n, dtype=torch.int32, device=device)
+        self.ws_bytes = gpulz_compress_batch_workspace_size(self.n, self.max_total, self.params)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.graph = None
+
+    def resolved(self, S):
+        if S not in (1, 2, 4, 8):
+            return (1, 1, 1, 4)
+        p = self.params[{1: 0, 2: 1, 4: 2, 8: 3}[S]]
+        d = gpulz_default_params(S)
+        return tuple(v if v else dv for v, dv in
+                     zip((p.chunk_symbols, p.window, p.min_match, p.waves_per_chunk), d))
+
+    def run(self, stream=None) -> None:
+        st = gpulz_compress_batch(self.n, self.d_in_ptrs.data_ptr(), self.d_in_bytes.data_ptr(),
+                                  self.d_widths.data_ptr(), self.params, self.d_out_ptrs.data_ptr(),
+                                  self.d_out_caps.data_ptr(), self.d_out_bytes.data_ptr(),
+                                  self.d_status.data_ptr(), self.max_total, self.ws.data_ptr(),
+                                  self.ws_bytes, _stream_handle(stream))
+        _check(st, "gpulz_compress_batch")
+
+    def capture(self) -> None:
+        torch = _torch()
+        self.run()  # warm up outside the capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+
+    def replay(self) -> None:
+        self.graph.replay()
+
+    def results(self):
+        """[(status, stream bytes as a uint8 device tensor or None)]"""
+        sizes = self.d_out_bytes.cpu().tolist()
+        stats = self.d_status.cpu().tolist()
+        return [(st, self.outputs[i][:sizes[i]] if st == GPULZ_OK else None)
+                for i, st in enumerate(stats)]
+
+
+class BatchDecompressor:
+    """One gpulz_decompress_batch call over fixed device streams."""
+
+    def __init__(self, streams, out_caps, device="cuda"):
+        torch = _torch()
+        self.streams = list(streams)
+        self.n = len(self.streams)
+        self.sizes = [t.numel() for t in self.streams]
+        self.max_total = max(sum(self.sizes), 1)
+        self.outputs = [torch.empty(max(c, 1), dtype=torch.uint8, device=device) for c in out_caps]
+        self.d_in_ptrs = _ptr_array(self.streams, device)
+        self.d_in_bytes = torch.tensor(self.sizes, dtype=torch.int64, device=device)
+        self.d_out_ptrs = _ptr_array(self.outputs, device)
+        self.d_out_caps = torch.tensor(list(out_caps), dtype=torch.int64, device=device)
+        self.d_out_bytes = torch.zeros(self.n, dtype=torch.int64, device=device)
+        self.d_status = torch.zeros(self.n, dtype=torch.int32, device=device)
+        self.ws_bytes = gpulz_decompress_batch_workspace_size(self.n, self.max_total)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def run(self, stream=None) -> None:
+        st = gpulz_decompress_batch(self.n, self.d_in_ptrs.data_ptr(), self.d_in_bytes.data_ptr(),
+                                    self.d_out_ptrs.data_ptr(), self.d_out_caps.data_ptr(),
+                                    self.d_out_bytes.data_ptr(), self.d_status.data_ptr(),
+                                    self.max_total, self.ws.data_ptr(), self.ws_bytes,
+                                    _stream_handle(stream))
+        _check(st, "gpulz_decompress_batch")
+
+    def results(self):
+        sizes = self.d_out_bytes.cpu().tolist()
+        stats = self.d_status.cpu().tolist()
+        return [(st, self.outputs[i][:sizes[i]] if st == GPULZ_OK else None)
+                for i, st in enumerate(stats)]

@@ -111,3 +111,47 @@ def test_decompress_rejects_bad_arguments():
         gpulz.GPULZ_ERR_INVALID_ARG
     assert gpulz.gpulz_decompress(FAKE, 4096, FAKE, 1 << 20, FAKE, None, FAKE, need) == \
         gpulz.GPULZ_ERR_INVALID_ARG
+
+
+def test_default_params_round_trip():
+    saved = gpulz.gpulz_default_params(2)
+    try:
+        gpulz.gpulz_set_default_params(2, 1024, 64, 3, 2)
+        assert gpulz.gpulz_default_params(2) == (1024, 64, 3, 2)
+        with pytest.raises(gpulz.GpulzError):
+            gpulz.gpulz_set_default_params(2, 0, 64, 3, 2)
+        with pytest.raises(gpulz.GpulzError):
+            gpulz.gpulz_set_default_params(2, 1024, 64, 3, 3)   # 3 waves is not a shape
+        with pytest.raises(gpulz.GpulzError):
+            gpulz.gpulz_default_params(3)
+    finally:
+        gpulz.gpulz_set_default_params(2, *saved)
+
+
+def test_batch_workspace_sizes():
+    a = gpulz.gpulz_compress_batch_workspace_size(10, 1 << 20)
+    b = gpulz.gpulz_compress_batch_workspace_size(10, 1 << 24)
+    assert 0 < a < b
+    p = {1: (512, 16, 2)}
+    assert gpulz.gpulz_compress_batch_workspace_size(10, 1 << 20, p) > a  # smaller chunks
+    with pytest.raises(gpulz.GpulzError):
+        gpulz.gpulz_compress_batch_workspace_size(10, 1 << 20, {4: (1 << 20, 16, 2)})
+    d1 = gpulz.gpulz_decompress_batch_workspace_size(10, 1 << 20)
+    assert 0 < d1 < gpulz.gpulz_decompress_batch_workspace_size(10, 1 << 30)
+
+
+def test_batch_rejects_bad_host_arguments():
+    ws = gpulz.gpulz_compress_batch_workspace_size(4, 4096)
+    ok = [4, FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, FAKE, 4096, FAKE, ws]
+    assert gpulz.gpulz_compress_batch(*(ok[:1] + [None] + ok[2:])) == gpulz.GPULZ_ERR_INVALID_ARG
+    assert gpulz.gpulz_compress_batch(*(ok[:-1] + [ws - 1])) == gpulz.GPULZ_ERR_WORKSPACE
+    assert gpulz.gpulz_compress_batch(*(ok[:10] + [FAKE + 8] + ok[11:])) == gpulz.GPULZ_ERR_INVALID_ARG
+    bad = gpulz.params_array({8: (8000, 64, 2)})
+    assert gpulz.gpulz_compress_batch(*(ok[:4] + [bad] + ok[5:])) == gpulz.GPULZ_ERR_INVALID_ARG
+    assert gpulz.gpulz_compress_batch(0, None, None, None, None, None, None, None, None, 0, None, 0) \
+        == gpulz.GPULZ_OK
+    dws = gpulz.gpulz_decompress_batch_workspace_size(4, 4096)
+    assert gpulz.gpulz_decompress_batch(4, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 4096, FAKE, dws - 1) \
+        == gpulz.GPULZ_ERR_WORKSPACE
+    assert gpulz.gpulz_decompress_batch(4, None, FAKE, FAKE, FAKE, FAKE, FAKE, 4096, FAKE, dws) \
+        == gpulz.GPULZ_ERR_INVALID_ARG
