@@ -8,6 +8,14 @@ record compaction). Prints one JSON line.
 Workload: float32 field 512 x 512 x 256 (sum of 8 random plane waves plus
 N(0, 1e-3) noise, quantised to 1e-4), 4-byte symbols, chunk 4096 symbols,
 window 256, minimum match 2 (seed 1).
+
+Other workloads (--workload), each printing its own JSON lines:
+  sweep   1 GiB per symbol width (Zipf bytes, Laplace uint16 codes, sorted
+          uint32 indices, float64 field), parameters from the autotuner;
+  batch   4096 buffers, log-uniform 4 KiB..64 MiB, mixed widths, one
+          graph-captured batch call against one gpulz_compress per buffer;
+  serve   Poisson stream of compress/decompress requests with continuous
+          batching under an HBM admission budget.
 """
 from __future__ import annotations
 
@@ -77,8 +85,153 @@ def cpu_baseline(x: np.ndarray, S: int, C: int, W: int, MIN: int, sample_bytes: 
                       f"input, single-threaded C oracle, {dt:.1f} s"}
 
 
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def pools_on_device(kinds, pool_bytes, seed0=100):
+    """Generate each content kind's pool once and keep it on the device."""
+    import torch
+    from paper_2304_07342_amd import synth
+    out = {}
+    for i, kind in enumerate(kinds):
+        S, gen = synth.POOL_KINDS[kind]
+        log(f"pool {kind} {pool_bytes >> 20} MiB")
+        host = gen(pool_bytes, seed0 + i)
+        out[kind] = torch.from_numpy(host[:pool_bytes]).to("cuda")
+        del host
+    return out
+
+
+def autotune_widths(pools, sample_bytes, log_fn=None):
+    from paper_2304_07342_amd import autotune, synth
+    samples = {}
+    for S, kinds in synth.WIDTH_KINDS.items():
+        samples[S] = pools[kinds[0]][:sample_bytes]
+    return autotune.tune(samples, log=log_fn)
+
+
+def run_sweep(args):
+    import torch
+    from paper_2304_07342_amd import autotune, gpulz, synth
+    size = args.sweep_bytes
+    kinds = {1: "zipf-u8", 2: "laplace-u16", 4: "sorted-u32", 8: "field-f64"}
+    for S, kind in kinds.items():
+        log(f"sweep {kind} {size >> 20} MiB")
+        x = torch.from_numpy(synth.POOL_KINDS[kind][1](size, 200 + S)[:size]).to("cuda")
+        tuned = autotune.tune_width(x[: min(size, 64 << 20)], S, log=log)
+        autotune.apply({S: tuned})
+        C, W, MIN, waves = tuned["chunk_symbols"], tuned["window"], tuned["min_match"], \
+            tuned["waves_per_chunk"]
+        comp = gpulz.Compressor(size, S, C, W, MIN)
+        comp.compress_async(x)
+        nbytes, status = comp.result()
+        assert status == gpulz.GPULZ_OK
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            comp.compress_async(x)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        d = gpulz.decompress(comp.out[:nbytes])
+        if not torch.equal(d, x):
+            raise SystemExit(f"round trip mismatch for {kind}")
+        print(json.dumps({"metric": "compress GB/s (input) + ratio", "workload": f"sweep-{kind}",
+                          "symbol_bytes": S, "input_bytes": size, "value": round(size / ms / 1e6, 3),
+                          "unit": "GB/s", "ms_per_step": round(ms, 4),
+                          "ratio": round(size / nbytes, 4), "chunk_symbols": C, "window": W,
+                          "min_match": MIN, "waves_per_chunk": waves,
+                          "autotune_candidates": len(tuned["measurements"])}), flush=True)
+        del x, comp, d
+        torch.cuda.empty_cache()
+
+
+def run_batch(args):
+    import torch
+    from paper_2304_07342_amd import gpulz, synth
+    pool_bytes = args.pool_mib << 20
+    spec = synth.batch_spec(args.nbufs, seed=3, pool_bytes=pool_bytes)
+    pools = pools_on_device(list(synth.POOL_KINDS), pool_bytes)
+    tuned = autotune_widths(pools, 32 << 20, log)
+    inputs = [pools[kind][off:off + n] for kind, S, off, n in spec]
+    widths = [S for _, S, _, _ in spec]
+    total = sum(n for _, _, _, n in spec)
+    log(f"batch of {len(spec)} buffers, {total / 2**30:.2f} GiB")
+    bc = gpulz.BatchCompressor(inputs, widths, None)
+    bc.capture()
+    stream = torch.cuda.current_stream()
+    bc.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        bc.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batched_ms = e0.elapsed_time(e1) / args.steps
+    res = bc.results()
+    assert all(st == gpulz.GPULZ_OK for st, _ in res)
+    z = sum(int(s.numel()) for _, s in res)
+
+    # plain: one gpulz_compress per buffer, same parameters, same stream
+    log("plain path")
+    params = {S: gpulz.gpulz_default_params(S) for S in (1, 2, 4, 8)}
+    max_ws = max(gpulz.gpulz_compress_workspace_size(n, S, params[S][0]) for _, S, _, n in spec)
+    ws = torch.empty(max_ws, dtype=torch.uint8, device="cuda")
+    meta = torch.zeros(2 * len(spec), dtype=torch.int64, device="cuda")
+    outs = [torch.empty_like(o) for o in bc.outputs]
+
+    def plain(record=None):
+        for i, (x, S) in enumerate(zip(inputs, widths)):
+            C, W, MIN, _ = params[S]
+            st = gpulz.gpulz_compress(x.data_ptr(), x.numel(), S, C, W, MIN, outs[i].data_ptr(),
+                                      bc.caps[i], meta[2 * i:].data_ptr(), meta[2 * i + 1:].data_ptr(),
+                                      ws.data_ptr(), max_ws, stream.cuda_stream)
+            assert st == gpulz.GPULZ_OK
+            if record is not None:
+                record[i].record(stream)
+    plain()
+    torch.cuda.synchronize()
+    ends = [torch.cuda.Event(enable_timing=True) for _ in spec]
+    p0 = torch.cuda.Event(enable_timing=True)
+    p0.record(stream)
+    plain(ends)
+    torch.cuda.synchronize()
+    done = sorted(p0.elapsed_time(e) for e in ends)
+    plain_ms = done[-1]
+    # the two paths must produce the same streams
+    sizes = meta.view(-1, 2)[:, 0].cpu().tolist()
+    for i, (st, s) in enumerate(res):
+        if sizes[i] != s.numel() or not torch.equal(outs[i][:sizes[i]], s):
+            raise SystemExit(f"batched and plain streams differ for buffer {i}")
+    pct = lambda v, q: v[min(len(v) - 1, int(q * len(v)))]
+    print(json.dumps({
+        "metric": "batched GB/s and p99 latency vs plain", "workload": "batch-4096",
+        "nbufs": len(spec), "input_bytes": total, "stream_bytes": z, "ratio": round(total / z, 4),
+        "batched_GBps": round(total / batched_ms / 1e6, 3), "batched_ms": round(batched_ms, 3),
+        "plain_GBps": round(total / plain_ms / 1e6, 3), "plain_ms": round(plain_ms, 3),
+        "speedup": round(plain_ms / batched_ms, 3),
+        "batched_completion_ms": {"p50": round(batched_ms, 3), "p99": round(batched_ms, 3)},
+        "plain_completion_ms": {"p50": round(pct(done, 0.5), 3), "p99": round(pct(done, 0.99), 3)},
+        "params": {str(S): list(p) for S, p in params.items()},
+        "autotune_GBps": {str(S): round(v["GBps"], 2) for S, v in tuned.items()}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="field", choices=["field", "sweep", "batch", "serve"])
+    ap.add_argument("--sweep-bytes", type=int, default=1 << 30)
+    ap.add_argument("--nbufs", type=int, default=4096)
+    ap.add_argument("--pool-mib", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--sweep-rates", type=float, nargs="*", default=[250.0, 500.0, 1000.0])
+    ap.add_argument("--sweep-seconds", type=float, default=10.0)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--serve-streams", type=int, default=128)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -93,6 +246,14 @@ def main():
         print("bench.py measures one GPU only; multi-GPU runs are not part of this build",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "sweep":
+        return run_sweep(args)
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "serve":
+        from paper_2304_07342_amd import serve
+        return serve.main_bench(args)
 
     import torch
     from paper_2304_07342_amd import gpulz, synth

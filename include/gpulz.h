@@ -100,6 +100,8 @@ gpulz_status gpulz_compress_workspace_size(uint64_t nbytes, uint32_t symbol_byte
  *                 stream is larger than out_capacity (then nothing is
  *                 written to d_out)
  *   d_workspace   at least gpulz_compress_workspace_size bytes
+ * The chunk encoder runs with the waves_per_chunk of the width's defaults
+ * (gpulz_default_params); that changes speed, never the bytes.
  * Asynchronous on `stream` (0 = null stream). Same bytes as any other
  * conforming producer for the same input and parameters. */
 gpulz_status gpulz_compress(const void* d_in, uint64_t nbytes, uint32_t symbol_bytes,

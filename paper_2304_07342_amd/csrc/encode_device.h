@@ -139,8 +139,9 @@ __device__ __forceinline__ void hit_step(const typename SymType<S>::T (&x)[16 / 
         acc[i] |= ballot(x[i] == q[i + V - j]);
       }
     }
-    // keep at most V compare masks live (more would spill SGPRs)
-    __builtin_amdgcn_sched_barrier(0);
+    // with 8 or 16 positions per lane, keep at most V compare masks live
+    // (more would spill SGPRs); wider symbols schedule better without it
+    if constexpr (S <= 2) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -254,10 +255,12 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
   uint32_t hw0 = 0;
   uint32_t hcache = hits[lane];
   while (p < c) {
-    // next hit at or after p
+    // next hit at or after p (first look at p's own bit in the cached words)
     uint32_t h = c;
-    {
-      const uint32_t pw = p >> 5;  // bitmap word holding position p
+    const uint32_t pw = p >> 5;  // bitmap word holding position p
+    if (pw - hw0 < 64u && ((readlane(hcache, pw - hw0) >> (p & 31u)) & 1u)) {
+      h = p;
+    } else {
       uint32_t w = pw;
       uint32_t first_bits = 0;
       for (;;) {
@@ -291,45 +294,70 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
     }
     if (h >= c) break;
 
-    // exact longest match at h
+    // exact longest match at h. Invariant: A holds the offsets d >= L whose
+    // match at h is at least L long; extending to L + 1 drops d = L and keeps
+    // the offsets that also match at h + L. Rows come four per LDS round trip
+    // from one per-lane base address (positions up to 3 past the chunk end
+    // read slack bytes and are never used).
     uint64_t A[WC];
+    if (h < 64u * WC) {
 #pragma unroll
-    for (int col = 0; col < WC; ++col) A[col] = wmask[col] & ballot(64u * col + lane + 1u <= h);
+      for (int col = 0; col < WC; ++col) A[col] = wmask[col] & ballot(64u * col + lane + 1u <= h);
+    } else {
+#pragma unroll
+      for (int col = 0; col < WC; ++col) A[col] = wmask[col];
+    }
     uint32_t L = 0;
     const uint32_t lim = min(kMaxMatch, c - h);
-    bool alive = true;
-    while (alive && L < lim) {
-      uint64_t R[4][WC];
+    while (L < lim) {
+      const uint32_t qb = h + L;
+      // this lane's window symbol for row r, column col: win[qb + r - (64 col + lane + 1)]
+      const T* wbase = win + (int)qb - (int)lane - 1 - 64 * (WC - 1);
+      T xr[4], wr[4][WC];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const uint32_t q = min(h + L + r, c - 1);
-        const T xq = win[q];
+        xr[r] = win[qb + r];
 #pragma unroll
-        for (int col = 0; col < WC; ++col) {
-          const uint32_t d = 64u * col + lane + 1u;
-          R[r][col] = ballot((win[(int)q - (int)d] == xq) & (d > L + r));
-        }
+        for (int col = 0; col < WC; ++col) wr[r][col] = wbase[r + 64 * (WC - 1 - col)];
       }
+      if (L + 4 <= 64) {
+        // offsets d <= L (only d = L can still be present) all sit in column 0
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (alive && L < lim) {
-          uint64_t any = 0;
+        for (int r = 0; r < 4; ++r) {
+          if (L >= lim) goto found;
           uint64_t B[WC];
 #pragma unroll
+          for (int col = 0; col < WC; ++col) B[col] = A[col] & ballot(wr[r][col] == xr[r]);
+          B[0] &= ~0ull << L;
+          uint64_t any = 0;
+#pragma unroll
+          for (int col = 0; col < WC; ++col) any |= B[col];
+          if (!any) goto found;
+#pragma unroll
+          for (int col = 0; col < WC; ++col) A[col] = B[col];
+          ++L;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (L >= lim) goto found;
+          uint64_t B[WC];
+          uint64_t any = 0;
+#pragma unroll
           for (int col = 0; col < WC; ++col) {
-            B[col] = A[col] & R[r][col];
+            const int sh = (int)L - 64 * col;  // offsets d <= L are too short
+            const uint64_t cap = sh <= 0 ? ~0ull : (sh >= 64 ? 0ull : (~0ull << sh));
+            B[col] = A[col] & ballot(wr[r][col] == xr[r]) & cap;
             any |= B[col];
           }
-          if (any) {
+          if (!any) goto found;
 #pragma unroll
-            for (int col = 0; col < WC; ++col) A[col] = B[col];
-            ++L;
-          } else {
-            alive = false;
-          }
+          for (int col = 0; col < WC; ++col) A[col] = B[col];
+          ++L;
         }
       }
     }
+  found:
     uint32_t val;
     if (L >= job.MIN) {
       uint32_t d = 0;

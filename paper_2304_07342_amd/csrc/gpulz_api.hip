@@ -57,9 +57,12 @@ uint64_t num_chunks(uint64_t nbytes, uint32_t S, uint32_t C) {
 // ---- per-width defaults and batch layouts ------------------------------------
 
 std::mutex g_defaults_mu;
+// Small chunks of dense (match-rich) data parse fastest with one wave per
+// workgroup (more chunks resident per CU); large literal-heavy chunks with
+// four (the hit bitmap is split across them).
 gpulz_params g_defaults[4] = {
-    {4096, 128, 2, 4},  // S = 1
-    {2048, 128, 2, 4},  // S = 2
+    {4096, 128, 2, 1},  // S = 1
+    {2048, 128, 2, 1},  // S = 2
     {4096, 256, 2, 4},  // S = 4
     {2048, 256, 2, 4},  // S = 8
 };
@@ -194,8 +197,13 @@ gpulz_status gpulz_compress(const void* d_in, uint64_t nbytes, uint32_t S, uint3
   e.slot_bytes = sl.slot_bytes;
   e.flag_area = sl.flag_area;
   e.sizes = reinterpret_cast<uint32_t*>(ws + w.sizes_off);
+  uint32_t waves;
+  {
+    std::lock_guard<std::mutex> lk(g_defaults_mu);
+    waves = g_defaults[width_index(S)].waves_per_chunk;
+  }
   int pi = prof_begin(0, stream);
-  if (launch_encode(e, S, N, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  if (launch_encode(e, S, N, waves, stream) != hipSuccess) return GPULZ_ERR_HIP;
   prof_end(pi, stream);
 
   ScanArgs sa;

@@ -87,7 +87,7 @@ struct ScatterArgs {
 };
 
 // Launchers (asynchronous; return the launch's hipError_t).
-hipError_t launch_encode(const EncodeArgs& a, uint32_t S, uint64_t N, hipStream_t s);
+hipError_t launch_encode(const EncodeArgs& a, uint32_t S, uint64_t N, uint32_t waves, hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
 size_t encode_lds_bytes(uint32_t C, uint32_t S, uint32_t W);

@@ -1,5 +1,5 @@
-// Single-buffer chunk encoder kernel: one workgroup of enc::kEncodeWaves
-// wavefronts per chunk (see encode_device.h for the steps).
+// Single-buffer chunk encoder kernel: one workgroup of 1, 2 or 4 wavefronts
+// per chunk (see encode_device.h for the steps).
 #include "encode_device.h"
 
 namespace gpulz {
@@ -24,18 +24,18 @@ __global__ __launch_bounds__(64 * enc::kEncodeWaves) void encode_kernel(EncodeAr
 }
 
 template <int S, int WC>
-hipError_t launch_sw(const EncodeArgs& a, uint64_t N, hipStream_t s) {
+hipError_t launch_sw(const EncodeArgs& a, uint64_t N, uint32_t waves, hipStream_t s) {
   const size_t lds = enc::lds_bytes<S, WC>(a.C);
-  hipLaunchKernelGGL((encode_kernel<S, WC>), dim3((uint32_t)N), dim3(64 * enc::kEncodeWaves), lds, s, a);
+  hipLaunchKernelGGL((encode_kernel<S, WC>), dim3((uint32_t)N), dim3(64 * waves), lds, s, a);
   return hipGetLastError();
 }
 template <int S>
-hipError_t launch_s(const EncodeArgs& a, uint64_t N, hipStream_t s) {
+hipError_t launch_s(const EncodeArgs& a, uint64_t N, uint32_t waves, hipStream_t s) {
   switch ((a.W + 63) / 64) {
-    case 1: return launch_sw<S, 1>(a, N, s);
-    case 2: return launch_sw<S, 2>(a, N, s);
-    case 3: return launch_sw<S, 3>(a, N, s);
-    default: return launch_sw<S, 4>(a, N, s);
+    case 1: return launch_sw<S, 1>(a, N, waves, s);
+    case 2: return launch_sw<S, 2>(a, N, waves, s);
+    case 3: return launch_sw<S, 3>(a, N, waves, s);
+    default: return launch_sw<S, 4>(a, N, waves, s);
   }
 }
 
@@ -46,13 +46,13 @@ size_t encode_lds_bytes(uint32_t C, uint32_t S, uint32_t W) {
   return align_up(64ull * wc * S + 16, 16) + enc::chunk_lds_bytes(C, S) + 4 * enc::hit_words(C, S);
 }
 
-hipError_t launch_encode(const EncodeArgs& a, uint32_t S, uint64_t N, hipStream_t s) {
+hipError_t launch_encode(const EncodeArgs& a, uint32_t S, uint64_t N, uint32_t waves, hipStream_t s) {
   if (N == 0) return hipSuccess;
   switch (S) {
-    case 1: return launch_s<1>(a, N, s);
-    case 2: return launch_s<2>(a, N, s);
-    case 4: return launch_s<4>(a, N, s);
-    default: return launch_s<8>(a, N, s);
+    case 1: return launch_s<1>(a, N, waves, s);
+    case 2: return launch_s<2>(a, N, waves, s);
+    case 4: return launch_s<4>(a, N, waves, s);
+    default: return launch_s<8>(a, N, waves, s);
   }
 }
 

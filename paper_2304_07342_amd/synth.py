@@ -84,18 +84,58 @@ def sinusoid_field(shape=(512, 512, 256), seed: int = 1, dtype=np.float32,
 
 def zipf_text(n: int, seed: int = 2, s: float = 1.2, ranks: int = 64) -> np.ndarray:
     """uint8 text-like bytes (TPC-H string stand-in): rank r in 1..`ranks`
-    drawn with probability proportional to r**-s, byte = 0x20 + r - 1."""
+    drawn with probability proportional to r**-s (inverse CDF of uniform
+    draws, 16 Mi at a time), byte = 0x20 + r - 1."""
     rng = _rng(seed)
     p = np.arange(1, ranks + 1, dtype=np.float64) ** -s
-    p /= p.sum()
-    return (0x20 + rng.choice(ranks, size=n, p=p)).astype(np.uint8)
+    cdf = np.cumsum(p / p.sum())
+    cdf[-1] = 1.0
+    out = np.empty(n, dtype=np.uint8)
+    step = 1 << 24
+    for i in range(0, n, step):
+        u = rng.random(min(step, n - i))
+        out[i:i + u.size] = 0x20 + np.searchsorted(cdf, u, side="right")
+    return out
 
 
 def sorted_indices(m: int, seed: int = 2, p: float = 0.3) -> np.ndarray:
     """uint32 strictly increasing indices (TPC-H int32 stand-in): the
-    cumulative sum of Geometric(p) gaps (each gap >= 1)."""
+    cumulative sum of Geometric(p) gaps (each gap >= 1), 16 Mi at a time."""
     rng = _rng(seed)
-    return np.cumsum(rng.geometric(p, size=m), dtype=np.uint64).astype(np.uint32)
+    out = np.empty(m, dtype=np.uint32)
+    carry = np.uint64(0)
+    step = 1 << 24
+    for i in range(0, m, step):
+        c = np.cumsum(rng.geometric(p, size=min(step, m - i)), dtype=np.uint64) + carry
+        out[i:i + c.size] = c.astype(np.uint32)
+        carry = c[-1]
+    return out
+
+
+def laplace_codes_pool(m: int, seed: int, copy_fraction: float = 0.30,
+                       batch: int = 1 << 15) -> np.ndarray:
+    """Large-scale variant of `laplace_codes` for benchmark pools: the same
+    Laplace codes and the same copy distributions (length U{2..32}, source
+    offset U{1..128}, periodic when the offset is shorter than the length),
+    but copies are applied `batch` at a time, each batch reading the codes as
+    they were before it (so copies within a batch do not see each other)."""
+    rng = _rng(seed)
+    v = np.clip(512 + np.rint(rng.laplace(0.0, 2.0, size=m)), 0, 1023).astype(np.uint16)
+    if m < 200:
+        return v
+    target = int(np.ceil(copy_fraction * m))
+    written = 0
+    while written < target:
+        L = rng.integers(2, 33, size=batch)
+        o = rng.integers(1, 129, size=batch)
+        dst = o + (rng.random(batch) * (m - 32 - o)).astype(np.int64)
+        k = np.arange(32)[None, :]
+        valid = k < L[:, None]
+        src = dst[:, None] - o[:, None] + (k % o[:, None])
+        d = (dst[:, None] + k)[valid]
+        v[d] = v[src[valid]]
+        written += int(L.sum())
+    return v
 
 
 def uniform_bytes(n: int, seed: int) -> np.ndarray:
@@ -160,6 +200,45 @@ def config0() -> np.ndarray:
 def config1() -> np.ndarray:
     """256 MiB float32 field 512 x 512 x 256, seed 1."""
     return sinusoid_field((512, 512, 256), seed=1, dtype=np.float32)
+
+
+def field64(shape=(256, 512, 256), seed: int = 8) -> np.ndarray:
+    """float64 version of the smooth field (same recipe)."""
+    return sinusoid_field(shape, seed=seed, dtype=np.float64)
+
+
+# Pools for the batched and serving workloads: one per content kind, device
+# buffers are slices of these (kind -> (symbol width, generator)).
+POOL_KINDS = {
+    "zipf-u8": (1, lambda nbytes, seed: zipf_text(nbytes, seed=seed)),
+    "laplace-u16": (2, lambda nbytes, seed: laplace_codes_pool(nbytes // 2, seed=seed).view(np.uint8)),
+    "sorted-u32": (4, lambda nbytes, seed: sorted_indices(nbytes // 4, seed=seed).view(np.uint8)),
+    "field-f32": (4, lambda nbytes, seed: sinusoid_field((nbytes // (4 * 512 * 256), 512, 256),
+                                                         seed=seed).view(np.uint8).reshape(-1)),
+    "field-f64": (8, lambda nbytes, seed: sinusoid_field((nbytes // (8 * 512 * 256), 512, 256),
+                                                         seed=seed, dtype=np.float64)
+                  .view(np.uint8).reshape(-1)),
+}
+# content kinds drawn for each symbol width (uniformly)
+WIDTH_KINDS = {1: ["zipf-u8"], 2: ["laplace-u16"], 4: ["sorted-u32", "field-f32"], 8: ["field-f64"]}
+
+
+def batch_spec(nbufs: int, seed: int, lo: int = 4 << 10, hi: int = 64 << 20,
+               pool_bytes: int = 256 << 20):
+    """Buffers for the batched workload: size log-uniform in [lo, hi] rounded
+    down to the symbol width, width uniform over {1, 2, 4, 8}, content kind by
+    width, and a random 16-byte aligned slice of that kind's pool. Returns a
+    list of (kind, width, offset, nbytes)."""
+    rng = _rng(seed)
+    out = []
+    for _ in range(nbufs):
+        S = int(rng.choice([1, 2, 4, 8]))
+        kind = WIDTH_KINDS[S][int(rng.integers(0, len(WIDTH_KINDS[S])))]
+        n = int(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        n = max(S, min(n, pool_bytes) // S * S)
+        off = int(rng.integers(0, pool_bytes - n + 1)) // 16 * 16
+        out.append((kind, S, off, n))
+    return out
 
 
 CONFIGS = {

@@ -191,3 +191,18 @@ def test_decoder_rejects_what_the_oracle_rejects(seed):
             assert gst == gpulz.GPULZ_OK and gdata == odata
         else:
             assert gst != gpulz.GPULZ_OK
+
+
+@pytest.mark.parametrize("S", [1, 2, 4, 8])
+def test_waves_per_chunk_does_not_change_bytes(S):
+    x = synth.mixed(200000, S, seed=S + 40)
+    saved = gpulz.gpulz_default_params(S)
+    _say("waves", S)
+    try:
+        outs = set()
+        for w in (1, 2, 4):
+            gpulz.gpulz_set_default_params(S, saved[0], saved[1], saved[2], w)
+            outs.add(gpu_compress(x, S, 1024, 200, 2)[1])
+        assert len(outs) == 1 and outs.pop() == oracle.compress(x, S, 1024, 200, 2)
+    finally:
+        gpulz.gpulz_set_default_params(S, *saved)
