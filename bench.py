@@ -10,6 +10,8 @@ N(0, 1e-3) noise, quantised to 1e-4), 4-byte symbols, chunk 4096 symbols,
 window 256, minimum match 2 (seed 1).
 
 Other workloads (--workload), each printing its own JSON lines:
+  small   1 MiB of uint16 Laplace codes (launch-latency bound): median of
+          single launches and of graph replays;
   sweep   1 GiB per symbol width (Zipf bytes, Laplace uint16 codes, sorted
           uint32 indices, float64 field), parameters from the autotuner;
   batch   4096 buffers, log-uniform 4 KiB..64 MiB, mixed widths, one
@@ -42,8 +44,8 @@ ENCODE_COUNTERS = {
     "fetch_kib": 131136.0, "fetch_scale": 2.0,
     "write_kib": 271756.25, "write_scale": 1.0,
 }
-ENCODE_SOURCES = ("paper_2304_07342_amd/csrc/lz_encode.hip", "paper_2304_07342_amd/csrc/wave.h",
-                  "paper_2304_07342_amd/csrc/gpulz_internal.h")
+ENCODE_SOURCES = ("paper_2304_07342_amd/csrc/lz_encode.hip", "paper_2304_07342_amd/csrc/encode_device.h",
+                  "paper_2304_07342_amd/csrc/wave.h", "paper_2304_07342_amd/csrc/gpulz_internal.h")
 
 
 def encode_traffic_bytes():
@@ -73,16 +75,31 @@ def window_compares(m: int, C: int, W: int) -> int:
     return full * per_chunk(C) + (per_chunk(last) if last else 0)
 
 
-def cpu_baseline(x: np.ndarray, S: int, C: int, W: int, MIN: int, sample_bytes: int):
+def cpu_threads() -> int:
+    """Host threads for the all-cores oracle run: the cores this process may
+    use, at most 16 (one GPU's share of a shared host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(x: np.ndarray, S: int, C: int, W: int, MIN: int, sample_bytes: int,
+                 threads: int = 1):
+    """The C oracle on the first `sample_bytes` of the input; with threads > 1
+    its chunks are spread over a thread pool (chunks are independent)."""
     import oracle
     oracle.build(force=False)
     sample = x[:sample_bytes]
     t0 = time.perf_counter()
-    oracle.compress(sample, S, C, W, MIN)
+    oracle.compress(sample, S, C, W, MIN, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": round(sample.size / dt / 1e9, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
+    kind = "single-threaded C oracle" if threads == 1 else f"C oracle over {threads} threads"
+    return {"value": round(sample.size / dt / 1e9, 6), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
             "sample": f"first {sample.size >> 20} MiB ({sample.size // (C * S)} chunks) of the same "
-                      f"input, single-threaded C oracle, {dt:.1f} s"}
+                      f"input, {kind}, {dt:.1f} s"}
 
 
 def log(*a):
@@ -146,6 +163,60 @@ def run_sweep(args):
                           "autotune_candidates": len(tuned["measurements"])}), flush=True)
         del x, comp, d
         torch.cuda.empty_cache()
+
+
+def run_small(args):
+    """1 MiB of uint16 codes: launch-latency bound, so report the median of
+    single launches and of graph replays of the same call."""
+    import torch
+    from paper_2304_07342_amd import gpulz, synth
+    cfg = synth.CONFIGS[0]
+    S, C, W, MIN = cfg["S"], cfg["C"], cfg["W"], cfg["MIN"]
+    x = torch.from_numpy(cfg["make"]().view(np.uint8).reshape(-1)).to("cuda")
+    n = x.numel()
+    comp = gpulz.Compressor(n, S, C, W, MIN)
+    stream = torch.cuda.current_stream()
+    reps = max(200, args.steps)
+
+    def median_ms(launch):
+        for _ in range(max(3, args.warmup)):
+            launch()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            launch()
+            b.record(stream)
+        torch.cuda.synchronize()
+        t = sorted(a.elapsed_time(b) for a, b in ev)
+        return t[len(t) // 2]
+
+    single = median_ms(lambda: comp.compress_async(x))
+    size, status = comp.result()
+    assert status == gpulz.GPULZ_OK
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        comp.compress_async(x)  # warm the launch path on the capture stream
+        side.synchronize()
+        with torch.cuda.graph(g, stream=side):
+            comp.compress_async(x)
+    stream.wait_stream(side)
+    graph = median_ms(g.replay)
+    size2, status2 = comp.result()
+    assert status2 == gpulz.GPULZ_OK and size2 == size
+    d = gpulz.decompress(comp.out[:size])
+    if not torch.equal(d, x):
+        raise SystemExit("round trip mismatch")
+    print(json.dumps({"metric": "compress GB/s (input) + ratio", "workload": cfg["name"],
+                      "input_bytes": n, "ratio": round(n / size, 4), "symbol_bytes": S,
+                      "chunk_symbols": C, "window": W, "min_match": MIN, "runs": reps,
+                      "single_launch_ms_p50": round(single, 4),
+                      "single_launch_GBps": round(n / single / 1e6, 3),
+                      "graph_replay_ms_p50": round(graph, 4),
+                      "graph_replay_GBps": round(n / graph / 1e6, 3)}), flush=True)
 
 
 def run_batch(args):
@@ -221,7 +292,8 @@ def run_batch(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="field", choices=["field", "sweep", "batch", "serve"])
+    ap.add_argument("--workload", default="field",
+                    choices=["field", "small", "sweep", "batch", "serve"])
     ap.add_argument("--sweep-bytes", type=int, default=1 << 30)
     ap.add_argument("--nbufs", type=int, default=4096)
     ap.add_argument("--pool-mib", type=int, default=256)
@@ -247,6 +319,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "small":
+        return run_small(args)
     if args.workload == "sweep":
         return run_sweep(args)
     if args.workload == "batch":
@@ -355,6 +429,9 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(x, S, C, W, MIN, args.cpu_sample_mib << 20)
+        th = cpu_threads()
+        if th > 1:
+            result["cpu_baseline_all_cores"] = cpu_baseline(x, S, C, W, MIN, n, threads=th)
     if args.profile_copy:
         ref = torch.empty_like(d_in)
         ref.copy_(d_in)

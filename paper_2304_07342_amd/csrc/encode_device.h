@@ -42,6 +42,9 @@ namespace enc {
 
 constexpr int kEncodeWaves = 4;
 
+// Match search at a hit: per-lane run lengths (true) or per-row offset masks.
+constexpr bool kRunSearch = true;
+
 // One chunk's work.
 struct ChunkJob {
   const uint8_t* src;   // first input byte of the chunk
@@ -85,6 +88,87 @@ __device__ __forceinline__ typename SymType<S>::T vec_elem(const uint4& v, int e
   } else {
     return (T)(w[e >> 2] >> (8 * (e & 3)));
   }
+}
+
+// 4 * S bytes (S = 1 or 2) from LDS at any byte address, read as aligned
+// dwords (wide LDS reads below dword alignment are slow) and funnel-shifted.
+template <int S>
+__device__ __forceinline__ typename SymType<4 * S>::T load4_sub(const void* p) {
+  const uint8_t* b = static_cast<const uint8_t*>(p);
+  const uint32_t sh = (uint32_t)(uintptr_t)b & 3u;
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(__builtin_assume_aligned(b - sh, 4));
+  const uint32_t w0 = w[0], w1 = w[1];
+  const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, sh);
+  if constexpr (S == 1) {
+    return lo;
+  } else {
+    const uint32_t w2 = w[2];
+    return (uint64_t)lo | ((uint64_t)__builtin_amdgcn_alignbyte(w2, w1, sh) << 32);
+  }
+}
+
+// Number of leading equal symbols (0..4) of the 4-symbol runs at a and b
+// (LDS, any symbol alignment).
+template <int S>
+__device__ __forceinline__ uint32_t lead_equal4(const typename SymType<S>::T* a,
+                                                const typename SymType<S>::T* b) {
+  if constexpr (S <= 2) {
+    using U = typename SymType<4 * S>::T;
+    const U x = load4_sub<S>(a), y = load4_sub<S>(b);
+    const U t = x ^ y;
+    if constexpr (S == 1) return t ? (uint32_t)__builtin_ctz(t) >> 3 : 4u;
+    else return t ? (uint32_t)__builtin_ctzll(t) >> 4 : 4u;
+  } else {
+    using T = typename SymType<S>::T;
+    T x[4], y[4];
+    __builtin_memcpy(x, a, 4 * S);
+    __builtin_memcpy(y, b, 4 * S);
+    return x[0] != y[0] ? 0u : x[1] != y[1] ? 1u : x[2] != y[2] ? 2u : x[3] != y[3] ? 3u : 4u;
+  }
+}
+
+// Exact longest match at chunk position h (h >= 1) over offsets
+// d <= min(W, h), lanes holding offsets (column col, lane l: d = 64 col + l
+// + 1). Each lane extends its own match four look-ahead symbols per LDS read
+// and stops at a mismatch or once its length reaches d (a match never
+// exceeds its offset). The wave maximum of (min(length, d, lim) << 9 | d)
+// is the longest length and, among equal lengths, the largest offset.
+// Returns that key (length = key >> 9, offset = key & 511).
+template <int S, int WC>
+__device__ __forceinline__ uint32_t match_key(const typename SymType<S>::T* win, uint32_t h,
+                                              uint32_t lim, uint32_t W, uint32_t lane) {
+  uint32_t len[WC];
+  bool alive[WC];
+#pragma unroll
+  for (int col = 0; col < WC; ++col) {
+    const uint32_t d = 64u * col + lane + 1u;
+    alive[col] = (d <= W) & (d <= h);
+    len[col] = 0;
+  }
+  for (uint32_t L0 = 0; L0 < lim; L0 += 4) {
+    // positions h + L0 - d + 3 >= -64 WC lie in the LDS pad before the
+    // chunk, h + L0 + 3 <= c + 2 in the slack after it
+    const typename SymType<S>::T* x = win + h + L0;
+    bool any = false;
+#pragma unroll
+    for (int col = 0; col < WC; ++col) {
+      const uint32_t d = 64u * col + lane + 1u;
+      const uint32_t r = lead_equal4<S>(x, x - d);
+      len[col] += alive[col] ? r : 0u;
+      alive[col] = alive[col] & (r == 4u) & (len[col] < d);
+      any |= alive[col];
+    }
+    if (ballot(any) == 0) break;
+  }
+  uint32_t key = 0;
+#pragma unroll
+  for (int col = 0; col < WC; ++col) {
+    const uint32_t d = 64u * col + lane + 1u;
+    const uint32_t Lc = min(min(len[col], d), lim);
+    const uint32_t k = (d <= W) & (d <= h) ? (Lc << 9) | d : 0u;
+    key = max(key, k);
+  }
+  return wave_max_u32(key);
 }
 
 // Token descriptors: bit 0 = pointer; literal: bits 1.. = chunk position;
@@ -294,82 +378,106 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
     }
     if (h >= c) break;
 
-    // exact longest match at h. Invariant: A holds the offsets d >= L whose
-    // match at h is at least L long; extending to L + 1 drops d = L and keeps
-    // the offsets that also match at h + L. Rows come four per LDS round trip
-    // from one per-lane base address (positions up to 3 past the chunk end
-    // read slack bytes and are never used).
-    uint64_t A[WC];
-    if (h < 64u * WC) {
-#pragma unroll
-      for (int col = 0; col < WC; ++col) A[col] = wmask[col] & ballot(64u * col + lane + 1u <= h);
-    } else {
-#pragma unroll
-      for (int col = 0; col < WC; ++col) A[col] = wmask[col];
-    }
-    uint32_t L = 0;
-    const uint32_t lim = min(kMaxMatch, c - h);
-    while (L < lim) {
-      const uint32_t qb = h + L;
-      // this lane's window symbol for row r, column col: win[qb + r - (64 col + lane + 1)]
-      const T* wbase = win + (int)qb - (int)lane - 1 - 64 * (WC - 1);
-      T xr[4], wr[4][WC];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        xr[r] = win[qb + r];
-#pragma unroll
-        for (int col = 0; col < WC; ++col) wr[r][col] = wbase[r + 64 * (WC - 1 - col)];
+    uint32_t val;
+    if constexpr (kRunSearch) {
+      const uint32_t key = match_key<S, WC>(win, h, min(kMaxMatch, c - h), job.W, lane);
+      const uint32_t L = key >> 9;
+      if (L >= job.MIN) {
+        val = 1u | (L << 1) | ((key & 0xFFu) << 9);
+        p = h + L;
+      } else {
+        val = h << 1;
+        p = h + 1;
       }
-      if (L + 4 <= 64) {
-        // offsets d <= L (only d = L can still be present) all sit in column 0
+    } else {
+      // exact longest match at h. Invariant: A holds the offsets d >= L whose
+      // match at h is at least L long; extending to L + 1 drops d = L and keeps
+      // the offsets that also match at h + L. Rows come four per LDS round trip
+      // from one per-lane base address (positions up to 3 past the chunk end
+      // read slack bytes and are never used).
+      uint64_t A[WC];
+      if (h < 64u * WC) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (L >= lim) goto found;
-          uint64_t B[WC];
-#pragma unroll
-          for (int col = 0; col < WC; ++col) B[col] = A[col] & ballot(wr[r][col] == xr[r]);
-          B[0] &= ~0ull << L;
-          uint64_t any = 0;
-#pragma unroll
-          for (int col = 0; col < WC; ++col) any |= B[col];
-          if (!any) goto found;
-#pragma unroll
-          for (int col = 0; col < WC; ++col) A[col] = B[col];
-          ++L;
-        }
+        for (int col = 0; col < WC; ++col) A[col] = wmask[col] & ballot(64u * col + lane + 1u <= h);
       } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (L >= lim) goto found;
-          uint64_t B[WC];
-          uint64_t any = 0;
+        for (int col = 0; col < WC; ++col) A[col] = wmask[col];
+      }
+      uint32_t L = 0;
+      const uint32_t lim = min(kMaxMatch, c - h);
+      while (L < lim) {
+        const uint32_t qb = h + L;
+        // this lane's window symbol for row r, column col: win[qb + r - (64 col + lane + 1)]
+        const T* wbase = win + (int)qb - (int)lane - 1 - 64 * (WC - 1);
+        T xr[4], wr[4][WC];
+        if constexpr (S <= 2) {
+          const auto xv = load4_sub<S>(win + qb);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) xr[r] = (T)(xv >> (8 * S * r));
 #pragma unroll
           for (int col = 0; col < WC; ++col) {
-            const int sh = (int)L - 64 * col;  // offsets d <= L are too short
-            const uint64_t cap = sh <= 0 ? ~0ull : (sh >= 64 ? 0ull : (~0ull << sh));
-            B[col] = A[col] & ballot(wr[r][col] == xr[r]) & cap;
-            any |= B[col];
-          }
-          if (!any) goto found;
+            const auto wv = load4_sub<S>(wbase + 64 * (WC - 1 - col));
 #pragma unroll
-          for (int col = 0; col < WC; ++col) A[col] = B[col];
-          ++L;
+            for (int r = 0; r < 4; ++r) wr[r][col] = (T)(wv >> (8 * S * r));
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            xr[r] = win[qb + r];
+#pragma unroll
+            for (int col = 0; col < WC; ++col) wr[r][col] = wbase[r + 64 * (WC - 1 - col)];
+          }
+        }
+        if (L + 4 <= 64) {
+          // offsets d <= L (only d = L can still be present) all sit in column 0
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (L >= lim) goto found;
+            uint64_t B[WC];
+#pragma unroll
+            for (int col = 0; col < WC; ++col) B[col] = A[col] & ballot(wr[r][col] == xr[r]);
+            B[0] &= ~0ull << L;
+            uint64_t any = 0;
+#pragma unroll
+            for (int col = 0; col < WC; ++col) any |= B[col];
+            if (!any) goto found;
+#pragma unroll
+            for (int col = 0; col < WC; ++col) A[col] = B[col];
+            ++L;
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (L >= lim) goto found;
+            uint64_t B[WC];
+            uint64_t any = 0;
+#pragma unroll
+            for (int col = 0; col < WC; ++col) {
+              const int sh = (int)L - 64 * col;  // offsets d <= L are too short
+              const uint64_t cap = sh <= 0 ? ~0ull : (sh >= 64 ? 0ull : (~0ull << sh));
+              B[col] = A[col] & ballot(wr[r][col] == xr[r]) & cap;
+              any |= B[col];
+            }
+            if (!any) goto found;
+#pragma unroll
+            for (int col = 0; col < WC; ++col) A[col] = B[col];
+            ++L;
+          }
         }
       }
-    }
-  found:
-    uint32_t val;
-    if (L >= job.MIN) {
-      uint32_t d = 0;
+    found:
+      if (L >= job.MIN) {
+        uint32_t d = 0;
 #pragma unroll
-      for (int col = WC - 1; col >= 0; --col) {
-        if (d == 0 && A[col]) d = 64u * col + 64u - (uint32_t)__clzll(A[col]);
+        for (int col = WC - 1; col >= 0; --col) {
+          if (d == 0 && A[col]) d = 64u * col + 64u - (uint32_t)__clzll(A[col]);
+        }
+        val = 1u | (L << 1) | ((d & 0xFFu) << 9);
+        p = h + L;
+      } else {
+        val = h << 1;
+        p = h + 1;
       }
-      val = 1u | (L << 1) | ((d & 0xFFu) << 9);
-      p = h + L;
-    } else {
-      val = h << 1;
-      p = h + 1;
     }
     if (lane == (ntok & 63u)) desc = val;
     ++ntok;

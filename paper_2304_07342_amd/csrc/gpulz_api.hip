@@ -72,10 +72,8 @@ int width_index(uint32_t S) { return S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : S ==
 bool valid_waves(uint32_t w) { return w == 1 || w == 2 || w == 4; }
 
 // Fills zero fields from the defaults and checks the result.
-bool resolve_params(const gpulz_params* in, WidthParams& wp, uint32_t& waves, size_t& lds) {
+bool resolve_params(const gpulz_params* in, WidthParams& wp) {
   std::lock_guard<std::mutex> lk(g_defaults_mu);
-  waves = 0;
-  lds = 0;
   for (int w = 0; w < 4; ++w) {
     const uint32_t S = 1u << w;
     gpulz_params p = in ? in[w] : gpulz_params{0, 0, 0, 0};
@@ -89,12 +87,10 @@ bool resolve_params(const gpulz_params* in, WidthParams& wp, uint32_t& waves, si
     wp.C[w] = p.chunk_symbols;
     wp.W[w] = p.window;
     wp.MIN[w] = p.min_match;
+    wp.waves[w] = p.waves_per_chunk;
     const SlotLayout sl = slot_layout(p.chunk_symbols, S, p.min_match);
     wp.slot_bytes[w] = sl.slot_bytes;
     wp.flag_area[w] = sl.flag_area;
-    waves = waves > p.waves_per_chunk ? waves : p.waves_per_chunk;
-    const size_t l = encode_lds_bytes(p.chunk_symbols, S, p.window);
-    lds = lds > l ? lds : l;
   }
   return true;
 }
@@ -112,6 +108,7 @@ BatchEncLayout batch_enc_layout(uint64_t nbufs, uint64_t max_total, const WidthP
   BatchEncLayout l;
   l.max_chunks = max_total / min_sc + nbufs;
   l.slot_cap = (uint64_t)((double)max_total * max_ratio) + nbufs * max_slot + 4096;
+  static_assert(sizeof(BatchCtrl) <= 256, "control block");
   l.ctrl_off = 0;
   l.bufs_off = 256;
   l.sizes_off = l.bufs_off + align_up(nbufs * sizeof(BatchEncBuf), 256);
@@ -320,9 +317,7 @@ gpulz_status gpulz_compress_batch_workspace_size(uint64_t nbufs, uint64_t max_to
                                                  const gpulz_params params_by_width[4],
                                                  size_t* ws_bytes) {
   WidthParams wp;
-  uint32_t waves;
-  size_t lds;
-  if (!ws_bytes || !resolve_params(params_by_width, wp, waves, lds)) return GPULZ_ERR_INVALID_ARG;
+  if (!ws_bytes || !resolve_params(params_by_width, wp)) return GPULZ_ERR_INVALID_ARG;
   *ws_bytes = (size_t)batch_enc_layout(nbufs, max_total_in_bytes, wp).total;
   return GPULZ_OK;
 }
@@ -338,9 +333,7 @@ gpulz_status gpulz_compress_batch(uint64_t nbufs, const void* const* d_in_ptrs,
       !d_status || nbufs > 0xFFFFFFFFull)
     return GPULZ_ERR_INVALID_ARG;
   WidthParams wp;
-  uint32_t waves;
-  size_t lds;
-  if (!resolve_params(params_by_width, wp, waves, lds)) return GPULZ_ERR_INVALID_ARG;
+  if (!resolve_params(params_by_width, wp)) return GPULZ_ERR_INVALID_ARG;
   if (!aligned(d_ws, 256)) return GPULZ_ERR_INVALID_ARG;
   const BatchEncLayout l = batch_enc_layout(nbufs, max_total_in_bytes, wp);
   if (!d_ws || ws_bytes < l.total) return GPULZ_ERR_WORKSPACE;
@@ -364,7 +357,7 @@ gpulz_status gpulz_compress_batch(uint64_t nbufs, const void* const* d_in_ptrs,
   a.max_chunks = l.max_chunks;
   a.slot_cap = l.slot_cap;
   int pi = prof_begin(5, stream);
-  if (launch_compress_batch(a, waves, lds, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  if (launch_compress_batch(a, stream) != hipSuccess) return GPULZ_ERR_HIP;
   prof_end(pi, stream);
   return GPULZ_OK;
 }

@@ -137,19 +137,22 @@ hipError_t launch_decode_chunks(const DecodeArgs& a, hipStream_t s);
 // ---- batches ----------------------------------------------------------------
 
 // Per-width parameters as the kernels see them (index = log2 S).
+// Per symbol width (index 0..3 for S = 1, 2, 4, 8).
 struct WidthParams {
-  uint32_t C[4], W[4], MIN[4];
+  uint32_t C[4], W[4], MIN[4], waves[4];
   uint64_t slot_bytes[4], flag_area[4];
 };
 
 struct BatchCtrl {
-  uint64_t ticket;      // next work item of the persistent kernel
-  uint64_t T;           // work items (chunks) in the batch
+  uint64_t ticket[4];   // next work item of each width's persistent encoder
+  uint64_t T[4];        // work items (chunks) of each width
+  uint64_t T_all;       // work items in the batch
   uint64_t slot_total;  // scratch slot bytes used
 };
 
 struct BatchEncBuf {
-  uint64_t chunk_base;  // first work item of this buffer
+  uint64_t chunk_base;     // first work item of this buffer
+  uint64_t width_base[4];  // chunks of each width in the buffers before this one
   uint64_t slot_base;   // its first scratch slot (bytes into the slot region)
   uint64_t n;           // input bytes
   uint64_t N;           // chunks
@@ -205,8 +208,7 @@ struct BatchDecArgs {
   uint64_t group_cap;
 };
 
-hipError_t launch_compress_batch(const BatchEncArgs& a, uint32_t waves, size_t lds_bytes,
-                                 hipStream_t s);
+hipError_t launch_compress_batch(const BatchEncArgs& a, hipStream_t s);
 hipError_t launch_decompress_batch(const BatchDecArgs& a, hipStream_t s);
 
 }  // namespace gpulz

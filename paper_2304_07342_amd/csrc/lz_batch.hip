@@ -4,10 +4,11 @@
 // can be captured in a HIP graph):
 //   plan     one workgroup validates every buffer, counts its chunks and
 //            prefix-sums chunk counts and scratch sizes over the buffers;
-//   encode   a persistent kernel: each workgroup takes (buffer, chunk) work
-//            items from an atomic ticket and runs the chunk encoder for the
-//            buffer's symbol width (uniform per workgroup), so thousands of
-//            uneven buffers share one launch and balance at chunk grain;
+//   encode   one persistent launch per symbol width: each workgroup takes
+//            (buffer, chunk) work items of that width from the width's atomic
+//            ticket, so thousands of uneven buffers balance at chunk grain,
+//            and every width runs with its own waves per chunk and LDS size
+//            (dense widths parse fastest with many 1-wave workgroups);
 //   scan     one workgroup per buffer prefix-sums its chunks' record sizes
 //            and writes its header, size and status;
 //   scatter  grid-stride over all chunks: table entry and record into the
@@ -68,11 +69,13 @@ __device__ inline uint64_t block_excl_scan(uint64_t v, uint64_t* scratch, uint64
 __global__ __launch_bounds__(kPlanThreads) void batch_enc_plan_kernel(BatchEncArgs a) {
   __shared__ uint64_t scratch[kPlanThreads / 64 + 1];
   uint64_t chunk_carry = 0, slot_carry = 0, byte_carry = 0;
+  uint64_t width_carry[4] = {0, 0, 0, 0};
   for (uint64_t b0 = 0; b0 < a.nbufs; b0 += blockDim.x) {
     const uint64_t b = b0 + threadIdx.x;
     BatchEncBuf e = {};
     e.status = kOk;
     uint64_t nb = 0;
+    uint32_t wi = 4;
     if (b < a.nbufs) {
       const uint32_t S = a.symbol_bytes[b];
       nb = a.in_bytes[b];
@@ -82,6 +85,7 @@ __global__ __launch_bounds__(kPlanThreads) void batch_enc_plan_kernel(BatchEncAr
       e.n = nb;
       if (ok) {
         const uint32_t w = width_index(S);
+        wi = w;
         e.S = S;
         e.C = a.wp.C[w];
         e.W = a.wp.W[w];
@@ -97,6 +101,13 @@ __global__ __launch_bounds__(kPlanThreads) void batch_enc_plan_kernel(BatchEncAr
     const uint64_t xc = block_excl_scan(e.N, scratch, &t_chunks);
     const uint64_t xs = block_excl_scan(e.N * e.slot_bytes, scratch, &t_slots);
     block_excl_scan(nb, scratch, &t_bytes);
+#pragma unroll
+    for (uint32_t w = 0; w < 4; ++w) {
+      uint64_t t_w;
+      const uint64_t xw = block_excl_scan(wi == w ? e.N : 0, scratch, &t_w);
+      e.width_base[w] = width_carry[w] + xw;
+      width_carry[w] += t_w;
+    }
     if (b < a.nbufs) {
       e.chunk_base = chunk_carry + xc;
       e.slot_base = slot_carry + xs;
@@ -116,9 +127,12 @@ __global__ __launch_bounds__(kPlanThreads) void batch_enc_plan_kernel(BatchEncAr
       a.bufs[b].status = kWorkspace;
     }
   }
+  if (threadIdx.x < 4) {
+    a.ctrl->ticket[threadIdx.x] = 0;
+    a.ctrl->T[threadIdx.x] = fits ? width_carry[threadIdx.x] : 0;
+  }
   if (threadIdx.x == 0) {
-    a.ctrl->ticket = 0;
-    a.ctrl->T = fits ? chunk_carry : 0;
+    a.ctrl->T_all = fits ? chunk_carry : 0;
     a.ctrl->slot_total = fits ? slot_carry : 0;
   }
 }
@@ -140,36 +154,23 @@ __device__ __forceinline__ void encode_item(const BatchEncArgs& a, uint64_t b, c
   enc::encode_chunk<S, WC>(job, lds);
 }
 
-template <int S>
-__device__ __forceinline__ void encode_item_s(const BatchEncArgs& a, uint64_t b, const BatchEncBuf& e,
-                                              uint64_t i, uint8_t* lds) {
-  switch ((e.W + 63) / 64) {
-    case 1: encode_item<S, 1>(a, b, e, i, lds); break;
-    case 2: encode_item<S, 2>(a, b, e, i, lds); break;
-    case 3: encode_item<S, 3>(a, b, e, i, lds); break;
-    default: encode_item<S, 4>(a, b, e, i, lds); break;
-  }
-}
-
+// Persistent encoder for the chunks of symbol width S (width index WI); the
+// window spans WC columns of 64 offsets (one window per width in a batch).
+template <int S, uint32_t WI, int WC>
 __global__ __launch_bounds__(64 * enc::kEncodeWaves) void batch_encode_kernel(BatchEncArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ uint64_t item;
-  const uint64_t T = a.ctrl->T;
+  const uint64_t T = a.ctrl->T[WI];
+  if (T == 0) return;
   for (;;) {
-    if (threadIdx.x == 0) item = atomicAdd((unsigned long long*)&a.ctrl->ticket, 1ull);
+    if (threadIdx.x == 0) item = atomicAdd((unsigned long long*)&a.ctrl->ticket[WI], 1ull);
     __syncthreads();
     const uint64_t g = item;
     __syncthreads();
     if (g >= T) break;
-    const uint64_t b = find_buffer(a.nbufs, g, [&](uint64_t k) { return a.bufs[k].chunk_base; });
+    const uint64_t b = find_buffer(a.nbufs, g, [&](uint64_t k) { return a.bufs[k].width_base[WI]; });
     const BatchEncBuf& e = a.bufs[b];
-    const uint64_t i = g - e.chunk_base;
-    switch (e.S) {
-      case 1: encode_item_s<1>(a, b, e, i, lds); break;
-      case 2: encode_item_s<2>(a, b, e, i, lds); break;
-      case 4: encode_item_s<4>(a, b, e, i, lds); break;
-      default: encode_item_s<8>(a, b, e, i, lds); break;
-    }
+    encode_item<S, WC>(a, b, e, g - e.width_base[WI], lds);
     __syncthreads();
   }
 }
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(1024) void batch_enc_scan_kernel(BatchEncArgs a) {
 }
 
 __global__ __launch_bounds__(256) void batch_scatter_kernel(BatchEncArgs a) {
-  const uint64_t T = a.ctrl->T;
+  const uint64_t T = a.ctrl->T_all;
   for (uint64_t g = blockIdx.x; g < T; g += gridDim.x) {
     const uint64_t b = find_buffer(a.nbufs, g, [&](uint64_t k) { return a.bufs[k].chunk_base; });
     const BatchEncBuf& e = a.bufs[b];
@@ -272,10 +273,7 @@ __global__ __launch_bounds__(kPlanThreads) void batch_dec_plan_kernel(BatchDecAr
       a.bufs[b].p.N = 0;
     }
   }
-  if (threadIdx.x == 0) {
-    a.ctrl->ticket = 0;
-    a.ctrl->T = fits ? chunk_carry : 0;
-  }
+  if (threadIdx.x == 0) a.ctrl->T_all = fits ? chunk_carry : 0;
 }
 
 __global__ __launch_bounds__(256) void batch_dec_table_kernel(BatchDecArgs a) {
@@ -303,7 +301,7 @@ __global__ __launch_bounds__(256) void batch_dec_table_kernel(BatchDecArgs a) {
 
 __global__ __launch_bounds__(64) void batch_decode_kernel(BatchDecArgs a) {
   __shared__ __align__(16) uint8_t ring[kDecodeRingBytes];
-  const uint64_t T = a.ctrl->T;
+  const uint64_t T = a.ctrl->T_all;
   for (uint64_t g = blockIdx.x; g < T; g += gridDim.x) {
     const uint64_t b = find_buffer(a.nbufs, g, [&](uint64_t k) { return a.bufs[k].chunk_base; });
     const BatchDecBuf& e = a.bufs[b];
@@ -330,20 +328,39 @@ int device_cus() {
 
 }  // namespace
 
-hipError_t launch_compress_batch(const BatchEncArgs& a, uint32_t waves, size_t lds_bytes,
-                                 hipStream_t s) {
+template <int S, uint32_t WI, int WC>
+hipError_t launch_width_wc(const BatchEncArgs& a, hipStream_t s) {
+  const uint32_t threads = 64 * a.wp.waves[WI];
+  const size_t lds = encode_lds_bytes(a.wp.C[WI], S, a.wp.W[WI]);
+  int per_cu = 0;
+  hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, batch_encode_kernel<S, WI, WC>, threads, lds);
+  if (err != hipSuccess) return err;
+  if (per_cu < 1) per_cu = 1;
+  hipLaunchKernelGGL((batch_encode_kernel<S, WI, WC>), dim3(device_cus() * per_cu), dim3(threads),
+                     lds, s, a);
+  return hipGetLastError();
+}
+
+template <int S, uint32_t WI>
+hipError_t launch_width(const BatchEncArgs& a, hipStream_t s) {
+  switch ((a.wp.W[WI] + 63) / 64) {
+    case 1: return launch_width_wc<S, WI, 1>(a, s);
+    case 2: return launch_width_wc<S, WI, 2>(a, s);
+    case 3: return launch_width_wc<S, WI, 3>(a, s);
+    default: return launch_width_wc<S, WI, 4>(a, s);
+  }
+}
+
+hipError_t launch_compress_batch(const BatchEncArgs& a, hipStream_t s) {
   if (a.nbufs == 0) return hipSuccess;
   hipLaunchKernelGGL(batch_enc_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  int per_cu = 0;
-  err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_encode_kernel, 64 * waves,
-                                                     lds_bytes);
-  if (err != hipSuccess) return err;
-  if (per_cu < 1) per_cu = 1;
-  hipLaunchKernelGGL(batch_encode_kernel, dim3(device_cus() * per_cu), dim3(64 * waves), lds_bytes,
-                     s, a);
-  if ((err = hipGetLastError()) != hipSuccess) return err;
+  if ((err = launch_width<1, 0>(a, s)) != hipSuccess) return err;
+  if ((err = launch_width<2, 1>(a, s)) != hipSuccess) return err;
+  if ((err = launch_width<4, 2>(a, s)) != hipSuccess) return err;
+  if ((err = launch_width<8, 3>(a, s)) != hipSuccess) return err;
   hipLaunchKernelGGL(batch_enc_scan_kernel, dim3((uint32_t)a.nbufs), dim3(1024), 0, s, a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   hipLaunchKernelGGL(batch_scatter_kernel, dim3(device_cus() * 16), dim3(256), 0, s, a);

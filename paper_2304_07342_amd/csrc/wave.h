@@ -49,6 +49,21 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
   return x;
 }
 
+// Maximum of `v` over the wave, returned as a wave-uniform value. DPP steps:
+// swap pairs, swap pairs of pairs, mirror within 8 and 16 lanes (every lane
+// then holds its 16-lane row's maximum), then the GFX9 row broadcasts fold
+// row 0 into row 1, row 2 into row 3, and lane 31 into rows 2 and 3, so lane
+// 63 holds the maximum of all four rows.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));
+  return readlane(v, 63);
+}
+
 // Orders this wave's LDS and global accesses before the ones that follow
 // (LDS is accessed in order within a wave; this keeps the compiler from
 // moving accesses across the point and waits for outstanding ones).
