@@ -42,8 +42,7 @@ hipError_t launch_s(const EncodeArgs& a, uint64_t N, uint32_t waves, hipStream_t
 }  // namespace
 
 size_t encode_lds_bytes(uint32_t C, uint32_t S, uint32_t W) {
-  const uint32_t wc = (W + 63) / 64;
-  return align_up(64ull * wc * S + 16, 16) + enc::chunk_lds_bytes(C, S) + 4 * enc::hit_words(C, S);
+  return enc::encode_lds(C, S, (W + 63) / 64);
 }
 
 hipError_t launch_encode(const EncodeArgs& a, uint32_t S, uint64_t N, uint32_t waves, hipStream_t s) {

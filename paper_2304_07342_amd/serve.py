@@ -307,6 +307,13 @@ def main_bench(args):
         assert st == gpulz.GPULZ_OK
         streams.append((s.clone(), x.numel()))
     del bc
+    # every prepared stream must decode back to its source
+    bd = gpulz.BatchDecompressor([s for s, _ in streams], [n for _, n in streams])
+    bd.run()
+    for (st, y), x in zip(bd.results(), srcs):
+        if st != gpulz.GPULZ_OK or not torch.equal(y, x):
+            raise SystemExit("a prepared decompress stream does not round-trip")
+    del bd
     torch.cuda.empty_cache()
     runs = [(args.serve_rate, args.serve_seconds)] + [(r, args.sweep_seconds) for r in args.sweep_rates]
     for rate, dur in runs:
