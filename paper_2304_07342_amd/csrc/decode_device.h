@@ -8,7 +8,16 @@
 //            chunks (one u64 per group; the sum must end exactly at the
 //            stream's end); a chunk's record offset is its group's offset
 //            plus a 64-lane prefix sum over the group's table entries;
-//   chunk    one wavefront per chunk walks the tokens 64 at a time: lane l
+//   chunk    (chunks of at most 4096 symbols and 16 KiB, the usual case) one
+//            workgroup of 256 threads per chunk: the record is staged into
+//            LDS with 16-byte loads; block-wide scans over the flag bits and
+//            the token lengths give every token's payload offset and output
+//            position at once, every rule is checked and the literals are
+//            written into an LDS copy of the chunk; wave 0 then copies the
+//            pointers in token order (a run of pointers whose sources are
+//            already final is copied together), and the chunk is written to
+//            HBM with 16-byte stores;
+//   chunk    (any other chunk) one wavefront walks the tokens 64 at a time: lane l
 //            takes token t + l, its flag bit gives its kind, mbcnt over the
 //            literal / pointer ballots gives its payload offset, a wave scan
 //            of the token lengths gives its output position. Literals are
@@ -180,6 +189,343 @@ __device__ bool decode_chunk(const uint8_t* flags, uint32_t F, uint32_t P, uint3
   if ((t + 7) / 8 != F || u != P) return false;
   if (t < 8ull * F && (flags[F - 1] >> (uint32_t)(t - 8ull * (F - 1))) != 0) return false;
   return true;
+}
+
+// ---- workgroup decoder ------------------------------------------------------
+
+constexpr uint32_t kDecThreads = 256;
+constexpr uint32_t kFastSyms = 16 * kDecThreads;          // tokens per chunk (16 per thread)
+constexpr uint32_t kFastOut = kDecodeRingBytes;           // chunk bytes kept in LDS
+constexpr uint32_t kFastRec = kFastSyms / 8 + kFastOut + 32;
+
+struct BlockLds {
+  uint8_t rec[kFastRec];              // staged record (16-byte aligned copy)
+  uint8_t out[kFastOut];              // the chunk; the ring of the wave decoder
+  uint64_t ptrbits[kFastSyms / 64];   // pointer flags of the decoded tokens
+  uint32_t scratch[16];
+};
+
+// Block-wide exclusive scan (sum) of one u32 per thread; `total` gets the sum.
+__device__ inline uint32_t block_excl_scan_u32(uint32_t v, uint32_t* scratch, uint32_t& total) {
+  const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint32_t incl = wave_incl_scan(v);
+  if (lane == 63) scratch[wid] = incl;
+  __syncthreads();
+  uint32_t before = 0;
+  total = 0;
+  for (uint32_t w = 0; w < nw; ++w) {
+    const uint32_t x = scratch[w];
+    before += w < wid ? x : 0u;
+    total += x;
+  }
+  __syncthreads();
+  return before + incl - v;
+}
+
+// Block-wide maximum and sum of one u32 each per thread, and any of a flag.
+__device__ inline void block_reduce(uint32_t& mx, uint32_t& sum, bool& any, uint32_t* scratch) {
+  const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint32_t wm = wave_max_u32(mx);
+  const uint32_t ws = readlane(wave_incl_scan(sum), 63);
+  const bool wa = ballot(any) != 0;
+  if (lane == 0) {
+    scratch[wid] = wm;
+    scratch[4 + wid] = ws;
+    scratch[8 + wid] = wa;
+  }
+  __syncthreads();
+  mx = 0;
+  sum = 0;
+  any = false;
+  for (uint32_t w = 0; w < nw; ++w) {
+    mx = max(mx, scratch[w]);
+    sum += scratch[4 + w];
+    any = any || scratch[8 + w];
+  }
+  __syncthreads();
+}
+
+// Whether the workgroup decoder takes a chunk of c symbols with F flag and
+// P payload bytes.
+__device__ inline bool fits_block(uint32_t c, uint32_t S, uint32_t F, uint32_t P) {
+  return c <= kFastSyms && c * S <= kFastOut && F <= kFastSyms / 8 && F + P + 16 <= kFastRec;
+}
+
+// One symbol of S bytes at any byte address in LDS (aligned dword reads and a
+// funnel shift; up to 11 bytes past the symbol are read).
+template <int S>
+__device__ __forceinline__ typename SymType<S>::T load_sym(const uint8_t* p) {
+  const uint32_t sh = (uint32_t)(uintptr_t)p & 3u;
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(__builtin_assume_aligned(p - sh, 4));
+  const uint32_t lo = __builtin_amdgcn_alignbyte(w[1], w[0], sh);
+  if constexpr (S == 8) {
+    return (uint64_t)lo | ((uint64_t)__builtin_amdgcn_alignbyte(w[2], w[1], sh) << 32);
+  } else {
+    return (typename SymType<S>::T)lo;
+  }
+}
+
+// Sum over the waves before this one of a wave-uniform value, and the total.
+__device__ inline uint32_t waves_excl(uint32_t v, uint32_t* scratch, uint32_t& total) {
+  const uint32_t wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane_id() == 0) scratch[wid] = v;
+  __syncthreads();
+  uint32_t before = 0;
+  total = 0;
+  for (uint32_t w = 0; w < nw; ++w) {
+    const uint32_t x = scratch[w];
+    before += w < wid ? x : 0u;
+    total += x;
+  }
+  __syncthreads();
+  return before;
+}
+
+// Decode one chunk with the whole workgroup (kDecThreads threads); returns
+// false (uniformly) if the chunk breaks a rule. rec: its record in HBM;
+// in_end: end of the stream (no byte at or past it is read); dst: its first
+// output byte.
+//
+// Token i (of the 8 F the flags describe) is handled by wave i / 1024 in
+// round (i / 64) % 16 on lane i % 64, so neighbouring lanes touch
+// neighbouring LDS bytes. Payload offsets come from the literal / pointer
+// counts (mbcnt within a round, running totals across rounds, one exchange
+// across waves); output positions likewise from the token lengths.
+template <int S>
+__device__ bool decode_chunk_block(const uint8_t* rec, const uint8_t* in_end, uint32_t F,
+                                   uint32_t P, uint32_t c, uint32_t W, uint32_t MIN, uint8_t* dst,
+                                   BlockLds& sm) {
+  using T = typename SymType<S>::T;
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  T* out = reinterpret_cast<T*>(sm.out);
+
+  // stage the record; the copy keeps the record's alignment within 16 bytes
+  const uint32_t a = (uint32_t)((uintptr_t)rec & 15u);
+  const uint8_t* g0 = rec - a;
+  const uint32_t nwords = (a + F + P + 15) / 16;
+  for (uint32_t k = tid; k < nwords; k += kDecThreads) {
+    const uint8_t* gp = g0 + 16 * k;
+    if (gp + 16 <= in_end) {
+      *reinterpret_cast<uint4*>(sm.rec + 16 * k) = *reinterpret_cast<const uint4*>(gp);
+    } else {
+      for (uint32_t b = 0; b < 16; ++b) sm.rec[16 * k + b] = gp + b < in_end ? gp[b] : 0;
+    }
+  }
+  __syncthreads();
+  const uint8_t* fl = sm.rec + a;
+  const uint8_t* pay = fl + F;
+  const uint32_t nt = 8 * F;
+  const uint32_t t0 = 1024 * wave + lane;
+
+  // token i's kind: pointer flag bit (only for i < 8 F)
+  auto is_ptr = [&](uint32_t i) { return i < nt && ((fl[i >> 3] >> (i & 7)) & 1u); };
+  // the wave's literal / pointer counts: its 1024 tokens are 128 flag bytes,
+  // two per lane
+  uint32_t np, nh;
+  {
+    const uint32_t i = 1024 * wave + 16 * lane;  // first of this lane's 16 tokens
+    uint32_t fb = 0;
+    if (i < nt) fb = fl[i >> 3];
+    if (i + 8 < nt) fb |= (uint32_t)fl[(i >> 3) + 1] << 8;
+    const uint32_t hmask = i >= nt ? 0u : (nt - i >= 16 ? 0xFFFFu : (1u << (nt - i)) - 1u);
+    np = readlane(wave_incl_scan((uint32_t)__popc(fb & hmask)), 63);
+    nh = readlane(wave_incl_scan((uint32_t)__popc(hmask)), 63);
+  }
+  uint32_t tot;
+  const uint32_t x1 = waves_excl((nh - np) | (np << 16), sm.scratch, tot);
+  const uint32_t lit0 = x1 & 0xFFFFu, ptr0 = x1 >> 16;
+
+  // this wave's total length: one per token, plus L - 1 per pointer whose
+  // payload is in range
+  uint32_t wlen = nh;
+  {
+    uint32_t lit = lit0, ptr = ptr0;
+    for (int j = 0; j < 16; ++j) {
+      const uint32_t i = t0 + 64 * j;
+      const bool isp = is_ptr(i);
+      const uint64_t pmj = ballot(isp), lm = ballot(i < nt && !isp);
+      if (pmj) {
+        const uint32_t off = S * (lit + mbcnt(lm)) + 2 * (ptr + mbcnt(pmj));
+        const uint32_t e = isp && off + 2 <= P ? pay[off] - 1u : 0u;
+        wlen += readlane(wave_incl_scan(e), 63);
+      }
+      lit += popc64(lm);
+      ptr += popc64(pmj);
+    }
+  }
+  uint32_t pos_end;
+  const uint32_t wpos0 = waves_excl(wlen, sm.scratch, pos_end);
+
+  // positions, checks and literals; taken tokens (position < c) are a prefix
+  bool bad = false;
+  uint32_t taken = 0, uend = 0;
+  {
+    uint32_t lit = lit0, ptr = ptr0, run = wpos0;
+    for (int j = 0; j < 16; ++j) {
+      const uint32_t i = t0 + 64 * j;
+      const bool has = i < nt;
+      const bool isp = is_ptr(i);
+      const uint64_t pmj = ballot(isp), lm = ballot(has && !isp);
+      const uint32_t off = S * (lit + mbcnt(lm)) + 2 * (ptr + mbcnt(pmj));
+      const uint32_t sz = isp ? 2u : (uint32_t)S;
+      const bool okp = off + sz <= P;
+      uint32_t L = 1, O = 1, pos;
+      if (pmj) {
+        if (isp && okp) {
+          L = pay[off];
+          O = pay[off + 1] ? pay[off + 1] : 256u;
+        }
+        const uint32_t len = has ? L : 0u;
+        const uint32_t inc = wave_incl_scan(len);
+        pos = run + inc - len;
+        run += readlane(inc, 63);
+      } else {
+        // no pointer in this round: consecutive positions
+        pos = run + lane;
+        run += popc64(lm);
+      }
+      const bool tk = has && pos < c;
+      if (tk) {
+        ++taken;
+        uend = max(uend, off + sz);
+        if (!okp) {
+          bad = true;
+        } else if (isp) {
+          bad = bad || !(L >= MIN && O <= W && O <= pos && L <= O && pos + L <= c);
+        } else {
+          out[pos] = load_sym<S>(pay + off);
+        }
+      }
+      const uint64_t tb = ballot(tk && isp);
+      if (lane == 0) sm.ptrbits[16 * wave + j] = tb;
+      lit += popc64(lm);
+      ptr += popc64(pmj);
+    }
+  }
+  uint32_t Tn = taken;
+  block_reduce(uend, Tn, bad, sm.scratch);
+  // every rule of the wave decoder: all checks above hold, the flags cover
+  // the chunk, the tokens use exactly F flag bytes and P payload bytes, and
+  // the unused flag bits are zero
+  if (bad || pos_end < c || (Tn + 7) / 8 != F || uend != P) return false;
+  if (Tn < nt && (fl[F - 1] >> (Tn - 8 * (F - 1))) != 0) return false;
+
+  // pointers, 64 at a time in token order, by wave 0. A pointer is copied
+  // once the last uncopied pointer before it ends at or before its source
+  // starts (destinations are ordered, so no uncopied output overlaps its
+  // source); the first uncopied pointer always qualifies.
+  if (wave == 0) {
+    const uint32_t nwd = (Tn + 63) / 64;
+    const uint64_t wd = lane < nwd ? sm.ptrbits[lane] : 0ull;
+    const uint32_t cnt = popc64(wd);
+    const uint32_t wb_incl = wave_incl_scan(cnt);
+    const uint32_t wb = wb_incl - cnt;  // pointers before flag word `lane`
+    const uint32_t NP = readlane(wb_incl, 63);
+    uint32_t extra = 0;
+    for (uint32_t g = 0; g < NP; g += 64) {
+      const uint32_t o = g + lane;  // this lane's pointer ordinal
+      const bool valid = o < NP;
+      // its flag word: the last word whose first ordinal is <= o
+      uint32_t lo = 0, hi = 63;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const uint32_t mid = (lo + hi + 1) / 2;
+        if ((uint32_t)__shfl((int)wb, (int)mid, 64) <= o) lo = mid;
+        else hi = mid - 1;
+      }
+      uint64_t m = __shfl((unsigned long long)wd, (int)lo, 64);
+      uint32_t r = o - (uint32_t)__shfl((int)wb, (int)lo, 64);
+      uint32_t bit = 0;
+#pragma unroll
+      for (uint32_t width = 32; width >= 1; width >>= 1) {
+        const uint32_t lowc = popc64(m & ((1ull << width) - 1));
+        if (r >= lowc) {
+          r -= lowc;
+          m >>= width;
+          bit += width;
+        }
+      }
+      const uint32_t t = 64 * lo + bit;
+      uint32_t L = 0, O = 0;
+      if (valid) {
+        const uint32_t off = S * (t - o) + 2 * o;
+        L = pay[off];
+        O = pay[off + 1] ? pay[off + 1] : 256u;
+      }
+      const uint32_t e = valid ? L - 1 : 0u;
+      const uint32_t inc = wave_incl_scan(e);
+      const uint32_t pos = t + extra + inc - e;
+      extra += readlane(inc, 63);
+      const uint32_t end = pos + L, src = pos - O;
+      uint64_t un = ballot(valid);
+      while (un) {
+        const uint64_t below = un & ((1ull << lane) - 1);
+        const uint32_t lk = below ? 63u - (uint32_t)__clzll(below) : 0u;
+        const uint32_t endk = (uint32_t)__shfl((int)end, (int)lk, 64);
+        const bool ready = ((un >> lane) & 1u) && (below == 0 || endk <= src);
+        const uint64_t rm = ballot(ready);
+        if (popc64(rm) == 1) {
+          const uint32_t j0 = (uint32_t)__ffsll((unsigned long long)rm) - 1;
+          const uint32_t P0 = readlane(pos, j0), Lj = readlane(L, j0), Oj = readlane(O, j0);
+          for (uint32_t k = lane; k < Lj; k += 64) out[P0 + k] = out[P0 - Oj + k];
+        } else if (ready) {
+          for (uint32_t k = 0; k < L; ++k) out[pos + k] = out[src + k];
+        }
+        wave_sync();
+        un &= ~rm;
+      }
+    }
+  }
+  __syncthreads();
+
+  // write the chunk out
+  const uint32_t nb = c * S;
+  if (((uintptr_t)dst & 15u) == 0) {
+    for (uint32_t k = tid; k < nb / 16; k += kDecThreads)
+      *reinterpret_cast<uint4*>(dst + 16 * k) = *reinterpret_cast<const uint4*>(sm.out + 16 * k);
+    for (uint32_t b = (nb & ~15u) + tid; b < nb; b += kDecThreads) dst[b] = sm.out[b];
+  } else {
+    for (uint32_t b = tid; b < nb; b += kDecThreads) dst[b] = sm.out[b];
+  }
+  return true;
+}
+
+// Decode chunk i of a validated stream of in_bytes bytes with the whole
+// workgroup; false (uniformly) if it is corrupt. Chunks the workgroup
+// decoder does not take go to the wave decoder on wave 0.
+__device__ inline bool decode_stream_chunk_block(const uint8_t* in, uint64_t in_bytes,
+                                                 const DecodeParams& p, const uint64_t* group_off,
+                                                 uint64_t i, uint8_t* out, BlockLds& sm) {
+  const uint8_t* e = in + kHeaderBytes + 8 * i;
+  const uint32_t F = *reinterpret_cast<const uint32_t*>(e);
+  const uint32_t P = *reinterpret_cast<const uint32_t*>(e + 4);
+  const uint8_t* rec = in + record_offset(in, group_off, i);
+  const uint64_t cs = i * p.C;
+  const uint32_t c = (uint32_t)min<uint64_t>(p.C, p.m - cs);
+  uint8_t* dst = out + cs * p.S;
+  if (fits_block(c, p.S, F, P)) {
+    switch (p.S) {
+      case 1: return decode_chunk_block<1>(rec, in + in_bytes, F, P, c, p.W, p.MIN, dst, sm);
+      case 2: return decode_chunk_block<2>(rec, in + in_bytes, F, P, c, p.W, p.MIN, dst, sm);
+      case 4: return decode_chunk_block<4>(rec, in + in_bytes, F, P, c, p.W, p.MIN, dst, sm);
+      default: return decode_chunk_block<8>(rec, in + in_bytes, F, P, c, p.W, p.MIN, dst, sm);
+    }
+  }
+  const uint32_t wave = threadIdx.x >> 6;
+  if (wave == 0) {
+    bool ok;
+    switch (p.S) {
+      case 1: ok = decode_chunk<1>(rec, F, P, c, p.W, p.MIN, reinterpret_cast<uint8_t*>(dst), sm.out); break;
+      case 2: ok = decode_chunk<2>(rec, F, P, c, p.W, p.MIN, reinterpret_cast<uint16_t*>(dst), sm.out); break;
+      case 4: ok = decode_chunk<4>(rec, F, P, c, p.W, p.MIN, reinterpret_cast<uint32_t*>(dst), sm.out); break;
+      default: ok = decode_chunk<8>(rec, F, P, c, p.W, p.MIN, reinterpret_cast<uint64_t*>(dst), sm.out); break;
+    }
+    if (lane_id() == 0) sm.scratch[15] = ok;
+  }
+  __syncthreads();
+  const bool ok = sm.scratch[15] != 0;
+  __syncthreads();
+  return ok;
 }
 
 // Decode chunk i of a validated stream (wave-wide); false if it is corrupt.

@@ -280,6 +280,7 @@ gpulz_status gpulz_decompress(const void* d_in, uint64_t in_bytes, void* d_out, 
   pa.status = d_status;
   DecodeArgs da;
   da.in = pa.in;
+  da.in_bytes = in_bytes;
   da.params = pa.params;
   da.group_off = pa.group_off;
   da.out = static_cast<uint8_t*>(d_out);

@@ -125,6 +125,7 @@ struct DecodePrepArgs {
 
 struct DecodeArgs {
   const uint8_t* in;
+  uint64_t in_bytes;
   const DecodeParams* params;
   const uint64_t* group_off;
   uint8_t* out;

@@ -299,17 +299,17 @@ __global__ __launch_bounds__(256) void batch_dec_table_kernel(BatchDecArgs a) {
   }
 }
 
-__global__ __launch_bounds__(64) void batch_decode_kernel(BatchDecArgs a) {
-  __shared__ __align__(16) uint8_t ring[kDecodeRingBytes];
+__global__ __launch_bounds__(dec::kDecThreads, 4) void batch_decode_kernel(BatchDecArgs a) {
+  __shared__ __align__(16) dec::BlockLds sm;
   const uint64_t T = a.ctrl->T_all;
   for (uint64_t g = blockIdx.x; g < T; g += gridDim.x) {
     const uint64_t b = find_buffer(a.nbufs, g, [&](uint64_t k) { return a.bufs[k].chunk_base; });
     const BatchDecBuf& e = a.bufs[b];
     if (e.p.status != kOk) continue;
-    const bool ok = dec::decode_stream_chunk(static_cast<const uint8_t*>(a.in_ptrs[b]), e.p,
-                                             a.group_off + e.group_base, g - e.chunk_base,
-                                             static_cast<uint8_t*>(a.out_ptrs[b]), ring);
-    if (!ok && lane_id() == 0) atomicExch(&a.status[b], kCorrupt);
+    const bool ok = dec::decode_stream_chunk_block(
+        static_cast<const uint8_t*>(a.in_ptrs[b]), a.in_bytes[b], e.p, a.group_off + e.group_base,
+        g - e.chunk_base, static_cast<uint8_t*>(a.out_ptrs[b]), sm);
+    if (!ok && threadIdx.x == 0) atomicExch(&a.status[b], kCorrupt);
   }
 }
 
@@ -377,7 +377,7 @@ hipError_t launch_decompress_batch(const BatchDecArgs& a, hipStream_t s) {
   if ((err = hipGetLastError()) != hipSuccess) return err;
   hipLaunchKernelGGL(batch_dec_table_kernel, dim3((uint32_t)a.nbufs), dim3(256), 0, s, a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  hipLaunchKernelGGL(batch_decode_kernel, dim3(device_cus() * 16), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(batch_decode_kernel, dim3(device_cus() * 4), dim3(dec::kDecThreads), 0, s, a);
   return hipGetLastError();
 }
 

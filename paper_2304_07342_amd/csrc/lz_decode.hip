@@ -2,14 +2,15 @@
 //   decode_prepare_kernel  one workgroup checks the header, prefix-sums the
 //                          table into per-group record offsets, checks the
 //                          sums and the output capacity;
-//   decode_kernel          one wavefront per chunk, grid-stride over chunks.
+//   decode_kernel          one workgroup of 256 threads per chunk, grid-stride
+//                          over chunks.
 #include "decode_device.h"
 
 namespace gpulz {
 namespace {
 
 constexpr uint32_t kPrepThreads = 1024;
-constexpr uint32_t kDecodeBlocks = 256 * 16;
+constexpr uint32_t kDecodeBlocks = 256 * 4;  // 4 workgroups of ~33 KiB LDS per CU
 
 __global__ __launch_bounds__(kPrepThreads) void decode_prepare_kernel(DecodePrepArgs a) {
   __shared__ DecodeParams P;
@@ -39,14 +40,14 @@ __global__ __launch_bounds__(kPrepThreads) void decode_prepare_kernel(DecodePrep
   }
 }
 
-__global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a) {
-  __shared__ __align__(16) uint8_t ring[kDecodeRingBytes];
+__global__ __launch_bounds__(dec::kDecThreads, 4) void decode_kernel(DecodeArgs a) {
+  __shared__ __align__(16) dec::BlockLds sm;
   const DecodeParams p = *a.params;
   if (p.status != kOk) return;
   if (blockIdx.x == 0 && threadIdx.x < p.r) a.out[p.m * p.S + threadIdx.x] = a.in[48 + threadIdx.x];
   for (uint64_t i = blockIdx.x; i < p.N; i += gridDim.x) {
-    const bool ok = dec::decode_stream_chunk(a.in, p, a.group_off, i, a.out, ring);
-    if (!ok && lane_id() == 0) atomicExch(a.status, kCorrupt);
+    const bool ok = dec::decode_stream_chunk_block(a.in, a.in_bytes, p, a.group_off, i, a.out, sm);
+    if (!ok && threadIdx.x == 0) atomicExch(a.status, kCorrupt);
   }
 }
 
@@ -58,7 +59,7 @@ hipError_t launch_decode_prepare(const DecodePrepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_decode_chunks(const DecodeArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(decode_kernel, dim3(kDecodeBlocks), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(decode_kernel, dim3(kDecodeBlocks), dim3(dec::kDecThreads), 0, s, a);
   return hipGetLastError();
 }
 
