@@ -528,24 +528,5 @@ __device__ inline bool decode_stream_chunk_block(const uint8_t* in, uint64_t in_
   return ok;
 }
 
-// Decode chunk i of a validated stream (wave-wide); false if it is corrupt.
-__device__ inline bool decode_stream_chunk(const uint8_t* in, const DecodeParams& p,
-                                           const uint64_t* group_off, uint64_t i, uint8_t* out,
-                                           uint8_t* ring) {
-  const uint8_t* e = in + kHeaderBytes + 8 * i;
-  const uint32_t F = *reinterpret_cast<const uint32_t*>(e);
-  const uint32_t P = *reinterpret_cast<const uint32_t*>(e + 4);
-  const uint8_t* rec = in + record_offset(in, group_off, i);
-  const uint64_t cs = i * p.C;
-  const uint32_t c = (uint32_t)min<uint64_t>(p.C, p.m - cs);
-  uint8_t* dst = out + cs * p.S;
-  switch (p.S) {
-    case 1: return decode_chunk<1>(rec, F, P, c, p.W, p.MIN, reinterpret_cast<uint8_t*>(dst), ring);
-    case 2: return decode_chunk<2>(rec, F, P, c, p.W, p.MIN, reinterpret_cast<uint16_t*>(dst), ring);
-    case 4: return decode_chunk<4>(rec, F, P, c, p.W, p.MIN, reinterpret_cast<uint32_t*>(dst), ring);
-    default: return decode_chunk<8>(rec, F, P, c, p.W, p.MIN, reinterpret_cast<uint64_t*>(dst), ring);
-  }
-}
-
 }  // namespace dec
 }  // namespace gpulz

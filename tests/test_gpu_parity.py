@@ -193,6 +193,27 @@ def test_decoder_rejects_what_the_oracle_rejects(seed):
             assert gst != gpulz.GPULZ_OK
 
 
+# Chunks beyond the workgroup decoder's limits (more than 4096 symbols, or
+# more than 16 KiB) are decoded one wavefront per chunk; fuzz that path too.
+@pytest.mark.parametrize("S,C", [(1, 6000), (4, 4500)])
+def test_wave_decoder_rejects_what_the_oracle_rejects(S, C):
+    rng = random.Random(S * 7 + C)
+    x = synth.mixed(3 * C * S // 2, S, seed=S + 90)
+    s = oracle.compress(x, S, C, 200, 2)
+    _say("wave decoder fuzz", S, C)
+    st, d, _, canary = gpu_decompress(s, x.size)
+    assert st == gpulz.GPULZ_OK and canary and d == x.tobytes()
+    for mut in _mutations(s, rng, 40):
+        cap = x.size + 64
+        ost, odata, _ = oracle.decompress_status(mut, capacity=cap)
+        gst, gdata, _, canary = gpu_decompress(mut, cap)
+        assert canary
+        if ost == oracle.OK:
+            assert gst == gpulz.GPULZ_OK and gdata == odata
+        else:
+            assert gst != gpulz.GPULZ_OK
+
+
 @pytest.mark.parametrize("S", [1, 2, 4, 8])
 def test_waves_per_chunk_does_not_change_bytes(S):
     x = synth.mixed(200000, S, seed=S + 40)
