@@ -33,28 +33,48 @@ __device__ inline uint8_t header_byte(uint32_t b, uint64_t n, uint32_t S, uint32
   return 0;
 }
 
-// Copies len bytes from a 4-byte aligned source to any destination: bytes up
-// to the first aligned destination word, whole aligned words in between
-// (each funnel-shifted from two source words), then the last bytes. Edge
-// bytes are written one by one so that neighbouring records that share a
-// destination word never overwrite each other. The source may be read up to
-// 4 bytes past its end.
+// Copies len bytes from a 16-byte aligned source to any destination: bytes
+// up to the first 16-byte aligned destination word, whole aligned 16-byte
+// words in between (each funnel-shifted from two source words), then the
+// last bytes. Edge bytes are written one by one so that neighbouring records
+// that share a destination word never overwrite each other. The source may
+// be read up to 16 bytes past its end (scratch slots keep that slack).
 __device__ inline void copy_bytes(uint8_t* dst, const uint8_t* src, uint32_t len, uint32_t tid,
                                   uint32_t nthreads) {
-  uint32_t head = (uint32_t)((4u - ((uintptr_t)dst & 3u)) & 3u);
+  // bytes up to dst's first 16-byte boundary
+  uint32_t head = (uint32_t)((16u - ((uintptr_t)dst & 15u)) & 15u);
   if (head > len) head = len;
-  if (tid < head) dst[tid] = src[tid];
-  const uint32_t body = (len - head) / 4;
-  uint32_t* dw = reinterpret_cast<uint32_t*>(dst + head);
-  const uint32_t* sw = reinterpret_cast<const uint32_t*>(src);
-  const uint32_t sh = head & 3u;
-  for (uint32_t k = tid; k < body; k += nthreads) {
-    const uint32_t o = (head + 4 * k) >> 2;
-    const uint32_t lo = sw[o];
-    dw[k] = sh ? __builtin_amdgcn_alignbyte(sw[o + 1], lo, sh) : lo;
+  for (uint32_t b = tid; b < head; b += nthreads) dst[b] = src[b];
+  // whole 16-byte words of dst; each one's source starts `head` bytes into
+  // a 16-byte source word (the same for all), so it is funnel-shifted out of
+  // two aligned source words
+  const uint32_t nw = (len - head) / 16;
+  uint4* d4 = reinterpret_cast<uint4*>(dst + head);
+  const uint4* s4 = reinterpret_cast<const uint4*>(src);
+  const uint32_t r = head & 3u;
+  switch (head >> 2) {
+#define GPULZ_COPY_CASE(Q)                                                                   \
+  case Q:                                                                                    \
+    for (uint32_t k = tid; k < nw; k += nthreads) {                                          \
+      const uint4 a = s4[k];                                                                 \
+      const uint4 b = (Q == 0 && r == 0) ? a : s4[k + 1];                                    \
+      const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};                        \
+      uint4 o;                                                                               \
+      o.x = __builtin_amdgcn_alignbyte(w[Q + 1], w[Q], r);                                   \
+      o.y = __builtin_amdgcn_alignbyte(w[Q + 2], w[Q + 1], r);                               \
+      o.z = __builtin_amdgcn_alignbyte(w[Q + 3], w[Q + 2], r);                               \
+      o.w = __builtin_amdgcn_alignbyte(w[Q + 4], w[Q + 3], r);                               \
+      d4[k] = o;                                                                             \
+    }                                                                                        \
+    break;
+    GPULZ_COPY_CASE(0)
+    GPULZ_COPY_CASE(1)
+    GPULZ_COPY_CASE(2)
+    GPULZ_COPY_CASE(3)
+#undef GPULZ_COPY_CASE
   }
-  const uint32_t done = head + 4 * body;
-  if (tid < len - done) dst[done + tid] = src[done + tid];
+  // the rest
+  for (uint32_t b = head + 16 * nw + tid; b < len; b += nthreads) dst[b] = src[b];
 }
 
 // Workgroup-wide exclusive scan of F_i + P_i over N chunks (sizes holds
