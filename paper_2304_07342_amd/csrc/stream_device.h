@@ -83,37 +83,64 @@ __device__ inline void copy_bytes(uint8_t* dst, const uint8_t* src, uint32_t len
 template <uint32_t ITEMS>
 __device__ inline uint64_t scan_record_sizes(const uint32_t* sizes, uint64_t N, uint64_t* offs,
                                              uint64_t* scratch) {
+  static_assert(ITEMS % 2 == 0, "items come in pairs (16-byte loads)");
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
   const uint32_t nw = blockDim.x >> 6;
   const uint64_t tile = (uint64_t)blockDim.x * ITEMS;
+  // a tile's record bytes fit in 32 bits (records are at most ~104 KB), so
+  // the scans inside a tile are 32-bit register (DPP) scans
+  // 16-byte loads and stores when both arrays are 16-byte aligned (a
+  // thread's first item index is a multiple of ITEMS, which is even)
+  const bool vec = (((uintptr_t)sizes | (uintptr_t)offs) & 15u) == 0;
   uint64_t carry = 0;
   for (uint64_t base = 0; base < N; base += tile) {
-    uint64_t v[ITEMS];
-    uint64_t local = 0;
+    const uint64_t i0 = base + (uint64_t)tid * ITEMS;  // this thread's first item
+    uint32_t v[ITEMS];
+    uint32_t local = 0;
+    if (vec && i0 + ITEMS <= N) {
+      const uint4* s4 = reinterpret_cast<const uint4*>(sizes + 2 * i0);
 #pragma unroll
-    for (uint32_t j = 0; j < ITEMS; ++j) {
-      const uint64_t i = base + (uint64_t)tid * ITEMS + j;
-      v[j] = i < N ? (uint64_t)sizes[2 * i] + sizes[2 * i + 1] : 0;
-      local += v[j];
+      for (uint32_t j = 0; j < ITEMS / 2; ++j) {
+        const uint4 q = s4[j];
+        v[2 * j] = q.x + q.y;
+        v[2 * j + 1] = q.z + q.w;
+      }
+    } else {
+#pragma unroll
+      for (uint32_t j = 0; j < ITEMS; ++j) {
+        const uint64_t i = i0 + j;
+        v[j] = i < N ? sizes[2 * i] + sizes[2 * i + 1] : 0u;
+      }
     }
-    const uint64_t incl = wave_incl_scan_u64(local);
+#pragma unroll
+    for (uint32_t j = 0; j < ITEMS; ++j) local += v[j];
+    const uint32_t incl = wave_incl_scan(local);
     if (lane == 63) scratch[wid] = incl;
     __syncthreads();
-    if (wid == 0) {
-      const uint64_t w = lane < nw ? scratch[lane] : 0;
-      const uint64_t wi = wave_incl_scan_u64(w);
-      if (lane < nw) scratch[lane] = wi - w;
-      if (lane == nw - 1) scratch[nw] = wi;
+    uint64_t before = 0, total = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+      const uint64_t x = scratch[w];
+      before += w < wid ? x : 0ull;
+      total += x;
     }
-    __syncthreads();
-    uint64_t run = carry + scratch[wid] + incl - local;
+    uint64_t run = carry + before + incl - local;
+    if (vec && i0 + ITEMS <= N) {
+      uint4* o4 = reinterpret_cast<uint4*>(offs + i0);
 #pragma unroll
-    for (uint32_t j = 0; j < ITEMS; ++j) {
-      const uint64_t i = base + (uint64_t)tid * ITEMS + j;
-      if (i < N) offs[i] = run;
-      run += v[j];
+      for (uint32_t j = 0; j < ITEMS / 2; ++j) {
+        const uint64_t a = run, b = run + v[2 * j];
+        run = b + v[2 * j + 1];
+        o4[j] = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+      }
+    } else {
+#pragma unroll
+      for (uint32_t j = 0; j < ITEMS; ++j) {
+        const uint64_t i = i0 + j;
+        if (i < N) offs[i] = run;
+        run += v[j];
+      }
     }
-    carry += scratch[nw];
+    carry += total;
     __syncthreads();
   }
   return carry;
