@@ -60,6 +60,15 @@ def _load():
                                         u64p]
         lib.oracle_compress_mt.restype = ctypes.c_int
         lib.oracle_compress_mt.argtypes = lib.oracle_compress.argtypes + [ctypes.c_int]
+        lib.oracle_compress_policy_mt.restype = ctypes.c_int
+        lib.oracle_compress_policy_mt.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint32,
+                                                  ctypes.c_uint32, ctypes.c_uint32,
+                                                  ctypes.c_uint32, ctypes.c_uint32, u8p,
+                                                  ctypes.c_uint64, u64p, ctypes.c_int]
+        lib.oracle_parse_chunk_policy.restype = ctypes.c_int64
+        lib.oracle_parse_chunk_policy.argtypes = [u8p, ctypes.c_uint32, ctypes.c_uint32,
+                                                  ctypes.c_uint32, ctypes.c_uint32,
+                                                  ctypes.c_uint32, u32p, u32p]
         lib.oracle_decompress.restype = ctypes.c_int
         lib.oracle_decompress.argtypes = [u8p, ctypes.c_uint64, u8p, ctypes.c_uint64, u64p]
         lib.oracle_parse_chunk.restype = ctypes.c_int64
@@ -84,8 +93,9 @@ def compress_bound(nbytes: int, symbol_bytes: int, chunk_symbols: int, min_match
 
 
 def compress_status(data, symbol_bytes: int, chunk_symbols: int, window: int, min_match: int,
-                    capacity: int | None = None, threads: int = 1):
-    """Return (status, stream_bytes_or_None, required_size)."""
+                    capacity: int | None = None, threads: int = 1, policy: int = 0):
+    """Return (status, stream_bytes_or_None, required_size). policy 0 = exact
+    longest match, 1 = the paper's single-pass window scan."""
     lib = _load()
     x = _as_bytes(data)
     n = x.size
@@ -94,7 +104,11 @@ def compress_status(data, symbol_bytes: int, chunk_symbols: int, window: int, mi
     out = np.zeros(max(cap, 1), dtype=np.uint8)
     out_len = ctypes.c_uint64(0)
     xin = x if n else np.zeros(1, dtype=np.uint8)
-    if threads > 1:
+    if policy != 0:
+        st = lib.oracle_compress_policy_mt(_u8(xin), n, symbol_bytes, chunk_symbols, window,
+                                           min_match, policy, _u8(out), cap,
+                                           ctypes.byref(out_len), max(1, threads))
+    elif threads > 1:
         st = lib.oracle_compress_mt(_u8(xin), n, symbol_bytes, chunk_symbols, window, min_match,
                                     _u8(out), cap, ctypes.byref(out_len), threads)
     else:
@@ -106,9 +120,9 @@ def compress_status(data, symbol_bytes: int, chunk_symbols: int, window: int, mi
 
 
 def compress(data, symbol_bytes: int, chunk_symbols: int, window: int, min_match: int,
-             threads: int = 1) -> bytes:
+             threads: int = 1, policy: int = 0) -> bytes:
     st, stream, _ = compress_status(data, symbol_bytes, chunk_symbols, window, min_match,
-                                    threads=threads)
+                                    threads=threads, policy=policy)
     if st != OK:
         raise ValueError(f"oracle_compress failed with status {st}")
     return stream
@@ -137,7 +151,7 @@ def decompress(stream) -> bytes:
     return data
 
 
-def parse_chunk(chunk, symbol_bytes: int, window: int, min_match: int):
+def parse_chunk(chunk, symbol_bytes: int, window: int, min_match: int, policy: int = 0):
     """Tokens of one chunk as a list of (length, offset); length 0 = literal."""
     lib = _load()
     x = _as_bytes(chunk)
@@ -145,9 +159,9 @@ def parse_chunk(chunk, symbol_bytes: int, window: int, min_match: int):
     lengths = np.zeros(max(c, 1), dtype=np.uint32)
     offsets = np.zeros(max(c, 1), dtype=np.uint32)
     xin = x if x.size else np.zeros(1, dtype=np.uint8)
-    t = lib.oracle_parse_chunk(_u8(xin), c, symbol_bytes, window, min_match,
-                               lengths.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
-                               offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    t = lib.oracle_parse_chunk_policy(_u8(xin), c, symbol_bytes, window, min_match, policy,
+                                      lengths.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                      offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
     if t < 0:
         raise ValueError("invalid parameters")
     return [(int(lengths[i]), int(offsets[i])) for i in range(t)]

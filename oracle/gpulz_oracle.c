@@ -89,18 +89,58 @@ static void best_match(const uint8_t* chunk, uint32_t c, uint32_t S, uint32_t W,
   *d_out = bestd;
 }
 
+/* Match policy 1: the paper's own single-pass search (section 3.3.2,
+ * matching steps 1-4). A window pointer w starts at the oldest window slot
+ * and a buffer pointer b at the coding position p. While the symbols at b
+ * and w are equal both advance and the current match grows (its offset is
+ * p - w at its first symbol). At a mismatch the current match replaces the
+ * best one if strictly longer, b returns to p, and w still advances by one,
+ * so the slot where a match failed is not retried as a match start. The
+ * walk ends when w reaches p (the match never exceeds its offset) or b
+ * reaches the chunk end. Readings where the paper is silent: the match in
+ * progress when the walk ends is compared too, and a match stops growing at
+ * 255 symbols (one-byte length field, section 2.2). */
+static void scan_match(const uint8_t* chunk, uint32_t c, uint32_t S, uint32_t W, uint32_t p,
+                       uint32_t* L_out, uint32_t* d_out) {
+  uint32_t w = p > W ? p - W : 0, b = p, len = 0, off = 0, bestL = 0, bestd = 0;
+  while (w < p && b < c) {
+    if (len < MAX_MATCH && sym_eq(chunk, b, w, S)) {
+      if (len == 0) off = p - w;
+      ++len;
+      ++b;
+    } else {
+      if (len > bestL) {
+        bestL = len;
+        bestd = off;
+      }
+      len = 0;
+      off = 0;
+      b = p;
+    }
+    ++w;
+  }
+  if (len > bestL) {
+    bestL = len;
+    bestd = off;
+  }
+  *L_out = bestL;
+  *d_out = bestd;
+}
+
 /* Steps 1-6 of section 2.2 on one chunk: start at the chunk's first symbol;
  * if the longest match is at least min_match long (the encoding step of
  * section 3.3.2), emit a pointer and advance by its length, else emit one
  * literal and advance by one. */
-int64_t oracle_parse_chunk(const uint8_t* chunk, uint32_t c, uint32_t S, uint32_t W,
-                           uint32_t MIN, uint32_t* lengths, uint32_t* offsets) {
+int64_t oracle_parse_chunk_policy(const uint8_t* chunk, uint32_t c, uint32_t S, uint32_t W,
+                                  uint32_t MIN, uint32_t policy, uint32_t* lengths,
+                                  uint32_t* offsets) {
   uint32_t p = 0;
   int64_t t = 0;
-  if (!valid_params(S, c ? c : 1, W, MIN)) return -1;
+  if (!valid_params(S, c ? c : 1, W, MIN) || policy > 1) return -1;
   while (p < c) {
     uint32_t L, d;
-    best_match(chunk, c, S, W, p, &L, &d);
+    if (policy == 0) best_match(chunk, c, S, W, p, &L, &d);
+    else scan_match(chunk, c, S, W, p, &L, &d);
     if (L >= MIN) {
       lengths[t] = L;
       offsets[t] = d;
@@ -113,6 +153,11 @@ int64_t oracle_parse_chunk(const uint8_t* chunk, uint32_t c, uint32_t S, uint32_
     ++t;
   }
   return t;
+}
+
+int64_t oracle_parse_chunk(const uint8_t* chunk, uint32_t c, uint32_t S, uint32_t W,
+                           uint32_t MIN, uint32_t* lengths, uint32_t* offsets) {
+  return oracle_parse_chunk_policy(chunk, c, S, W, MIN, 0, lengths, offsets);
 }
 
 /* Serialise one parsed chunk: flag bytes (one bit per token, 1 = pointer,
@@ -162,7 +207,8 @@ uint64_t oracle_compress_bound(uint64_t n, uint32_t S, uint32_t C, uint32_t MIN)
 }
 
 static void write_header(uint8_t* h, uint64_t n, uint32_t S, uint32_t C, uint32_t W,
-                         uint32_t MIN, uint64_t N, uint64_t total, const uint8_t* tail) {
+                         uint32_t MIN, uint32_t policy, uint64_t N, uint64_t total,
+                         const uint8_t* tail) {
   uint32_t r = (uint32_t)(n % S), k;
   memset(h, 0, HDR_BYTES);
   h[0] = 'G';
@@ -171,7 +217,7 @@ static void write_header(uint8_t* h, uint64_t n, uint32_t S, uint32_t C, uint32_
   h[3] = '1';
   put_u16(h + 4, 1);      /* version */
   h[6] = (uint8_t)S;      /* symbol bytes */
-  h[7] = 0;               /* match policy: exact longest match */
+  h[7] = (uint8_t)policy; /* match policy: 0 exact longest match, 1 single-pass scan */
   put_u32(h + 8, C);      /* chunk symbols */
   put_u16(h + 12, W);     /* window (256 fits the u16 field) */
   h[14] = (uint8_t)MIN;   /* minimum match */
@@ -186,7 +232,7 @@ static void write_header(uint8_t* h, uint64_t n, uint32_t S, uint32_t C, uint32_
 typedef struct {
   const uint8_t* x;
   uint64_t m;
-  uint32_t S, C, W, MIN;
+  uint32_t S, C, W, MIN, policy;
   uint64_t first, last; /* chunk range [first, last) */
   uint8_t* recs;        /* records at chunk slots of `slot` bytes */
   uint64_t slot;
@@ -210,7 +256,7 @@ static void* run_job(void* arg) {
     uint64_t cs = i * j->C;
     uint32_t c = (uint32_t)((j->m - cs) < j->C ? (j->m - cs) : j->C);
     const uint8_t* chunk = j->x + cs * j->S;
-    int64_t T = oracle_parse_chunk(chunk, c, j->S, j->W, j->MIN, lengths, offsets);
+    int64_t T = oracle_parse_chunk_policy(chunk, c, j->S, j->W, j->MIN, j->policy, lengths, offsets);
     encode_record(chunk, j->S, T, lengths, offsets, j->recs + i * j->slot, &j->F[i], &j->P[i]);
   }
   free(lengths);
@@ -219,13 +265,14 @@ static void* run_job(void* arg) {
 }
 
 static int compress_impl(const uint8_t* x, uint64_t n, uint32_t S, uint32_t C, uint32_t W,
-                         uint32_t MIN, uint8_t* out, uint64_t capacity, uint64_t* out_len,
-                         int threads) {
+                         uint32_t MIN, uint32_t policy, uint8_t* out, uint64_t capacity,
+                         uint64_t* out_len, int threads) {
   uint64_t m, N, slot, total, i, pos;
   uint8_t* recs;
   uint32_t *F, *P;
   int status = ORACLE_OK, t;
-  if (!out_len || (n && !x) || !valid_params(S, C, W, MIN)) return ORACLE_ERR_INVALID_ARG;
+  if (!out_len || (n && !x) || !valid_params(S, C, W, MIN) || policy > 1)
+    return ORACLE_ERR_INVALID_ARG;
   m = n / S;
   N = (m + C - 1) / C;
   slot = (C + 7) / 8 + (uint64_t)C * ((S == 1 && MIN == 1) ? 2 : S);
@@ -258,6 +305,7 @@ static int compress_impl(const uint8_t* x, uint64_t n, uint32_t S, uint32_t C, u
       jobs[t].C = C;
       jobs[t].W = W;
       jobs[t].MIN = MIN;
+      jobs[t].policy = policy;
       jobs[t].first = N * (uint64_t)t / (uint64_t)threads;
       jobs[t].last = N * (uint64_t)(t + 1) / (uint64_t)threads;
       jobs[t].recs = recs;
@@ -283,7 +331,7 @@ static int compress_impl(const uint8_t* x, uint64_t n, uint32_t S, uint32_t C, u
     if (total > capacity || !out) {
       status = ORACLE_ERR_OUT_OF_SPACE;
     } else {
-      write_header(out, n, S, C, W, MIN, N, total, x + (n - n % S));
+      write_header(out, n, S, C, W, MIN, policy, N, total, x + (n - n % S));
       pos = HDR_BYTES + 8 * N;
       for (i = 0; i < N; ++i) {
         put_u32(out + HDR_BYTES + 8 * i, F[i]);
@@ -301,13 +349,25 @@ static int compress_impl(const uint8_t* x, uint64_t n, uint32_t S, uint32_t C, u
 
 int oracle_compress(const uint8_t* x, uint64_t n, uint32_t S, uint32_t C, uint32_t W,
                     uint32_t MIN, uint8_t* out, uint64_t capacity, uint64_t* out_len) {
-  return compress_impl(x, n, S, C, W, MIN, out, capacity, out_len, 1);
+  return compress_impl(x, n, S, C, W, MIN, 0, out, capacity, out_len, 1);
+}
+
+int oracle_compress_policy(const uint8_t* x, uint64_t n, uint32_t S, uint32_t C, uint32_t W,
+                           uint32_t MIN, uint32_t policy, uint8_t* out, uint64_t capacity,
+                           uint64_t* out_len) {
+  return compress_impl(x, n, S, C, W, MIN, policy, out, capacity, out_len, 1);
 }
 
 int oracle_compress_mt(const uint8_t* x, uint64_t n, uint32_t S, uint32_t C, uint32_t W,
                        uint32_t MIN, uint8_t* out, uint64_t capacity, uint64_t* out_len,
                        int threads) {
-  return compress_impl(x, n, S, C, W, MIN, out, capacity, out_len, threads);
+  return compress_impl(x, n, S, C, W, MIN, 0, out, capacity, out_len, threads);
+}
+
+int oracle_compress_policy_mt(const uint8_t* x, uint64_t n, uint32_t S, uint32_t C, uint32_t W,
+                              uint32_t MIN, uint32_t policy, uint8_t* out, uint64_t capacity,
+                              uint64_t* out_len, int threads) {
+  return compress_impl(x, n, S, C, W, MIN, policy, out, capacity, out_len, threads);
 }
 
 /* Inverse of the parse: replay the tokens of every chunk. The paper only
@@ -325,7 +385,7 @@ int oracle_decompress(const uint8_t* in, uint64_t in_len, uint8_t* out, uint64_t
   if (in[0] != 'G' || in[1] != 'L' || in[2] != 'Z' || in[3] != '1') return ORACLE_ERR_CORRUPT;
   if (get_u16(in + 4) != 1) return ORACLE_ERR_CORRUPT;
   S = in[6];
-  if (in[7] != 0) return ORACLE_ERR_CORRUPT;
+  if (in[7] > 1) return ORACLE_ERR_CORRUPT; /* match policy 0 or 1 */
   C = get_u32(in + 8);
   W = get_u16(in + 12);
   MIN = in[14];

@@ -14,6 +14,8 @@
  *     Kernel I encoding step), else emit one literal symbol;
  *   - symbols are S = 1, 2, 4 or 8 raw bytes (section 3.2.3, multi-byte
  *     matching);
+ *   - match policy 1 replaces the longest match by the paper's own
+ *     single-pass window scan (section 3.3.2, matching steps 1-4);
  *   - the input is split into independent chunks of C symbols; no match
  *     crosses a chunk boundary and the window is empty at each chunk start
  *     (section 3.3.1, data chunks; section 2.2, the window starts empty);
@@ -73,6 +75,22 @@ int oracle_decompress(const uint8_t* in, uint64_t in_len, uint8_t* out,
 int64_t oracle_parse_chunk(const uint8_t* chunk, uint32_t c, uint32_t symbol_bytes,
                            uint32_t window, uint32_t min_match,
                            uint32_t* lengths, uint32_t* offsets);
+
+/* Compress with match policy 0 (the exact longest match, as oracle_compress)
+ * or 1 (the paper's single-pass window scan of section 3.3.2, see
+ * scan_match in the source). The policy is recorded in header byte 7. */
+int oracle_compress_policy(const uint8_t* x, uint64_t n, uint32_t symbol_bytes,
+                           uint32_t chunk_symbols, uint32_t window, uint32_t min_match,
+                           uint32_t policy, uint8_t* out, uint64_t capacity, uint64_t* out_len);
+int oracle_compress_policy_mt(const uint8_t* x, uint64_t n, uint32_t symbol_bytes,
+                              uint32_t chunk_symbols, uint32_t window, uint32_t min_match,
+                              uint32_t policy, uint8_t* out, uint64_t capacity,
+                              uint64_t* out_len, int threads);
+
+/* oracle_parse_chunk with an explicit match policy (0 or 1). */
+int64_t oracle_parse_chunk_policy(const uint8_t* chunk, uint32_t c, uint32_t symbol_bytes,
+                                  uint32_t window, uint32_t min_match, uint32_t policy,
+                                  uint32_t* lengths, uint32_t* offsets);
 
 /* Compress with the input split across `threads` POSIX threads by chunk
  * range (chunks are independent). Same output as oracle_compress; used only

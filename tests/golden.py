@@ -34,14 +34,14 @@ def _tokens(items):
 
 
 def load(path):
-    v = {"name": os.path.basename(path), "tail": b""}
+    v = {"name": os.path.basename(path), "tail": b"", "policy": 0}
     for line in open(path):
         line = line.strip()
         if not line or line.startswith("#"):
             continue
         key, _, rest = line.partition(" ")
         items = rest.split()
-        if key in ("S", "C", "W", "MIN", "total"):
+        if key in ("S", "C", "W", "MIN", "total", "policy"):
             v[key] = int(items[0])
         elif key in ("input", "body", "tail"):
             v[key] = _hexlist(items)

@@ -42,12 +42,37 @@ def brute_best(chunk, p: int, W: int):
     return best
 
 
-def parse(chunk, W: int, MIN: int):
+def scan_best(chunk, p: int, W: int):
+    """Match policy 1, the paper's single pass over the window (section
+    3.3.2, matching steps 1-4): walk the window once from its oldest slot;
+    a run of equal symbols (window slot vs. look-ahead) is a candidate that
+    wins only if strictly longer; after a failed symbol the look-ahead starts
+    over at p and the walk continues at the next slot. The run still open
+    when the walk stops counts too; runs stop at 255 symbols."""
+    best = (0, 0)
+    run, run_from = 0, 0
+    for w in range(max(0, p - W), p):
+        if p + run >= len(chunk):
+            break
+        if run < 255 and chunk[p + run] == chunk[w]:
+            if run == 0:
+                run_from = w
+            run += 1
+            continue
+        if run > best[0]:
+            best = (run, p - run_from)
+        run = 0
+    if run > best[0]:
+        best = (run, p - run_from)
+    return best
+
+
+def parse(chunk, W: int, MIN: int, policy: int = 0):
     """Greedy parse: list of (L, d) with L = 0 meaning a literal."""
     toks = []
     p = 0
     while p < len(chunk):
-        L, d = brute_best(chunk, p, W)
+        L, d = brute_best(chunk, p, W) if policy == 0 else scan_best(chunk, p, W)
         if L >= MIN:
             toks.append((L, d))
             p += L
@@ -73,26 +98,28 @@ def record(chunk, toks, S: int) -> tuple[bytes, int, int]:
     return bytes(flags) + bytes(payload), len(flags), len(payload)
 
 
-def header(n: int, S: int, C: int, W: int, MIN: int, N: int, total: int, tail: bytes) -> bytes:
-    h = b"GLZ1" + struct.pack("<HBBIHBBQQQB", 1, S, 0, C, W, MIN, 255, n, N, total, len(tail))
+def header(n: int, S: int, C: int, W: int, MIN: int, N: int, total: int, tail: bytes,
+           policy: int = 0) -> bytes:
+    h = b"GLZ1" + struct.pack("<HBBIHBBQQQB", 1, S, policy, C, W, MIN, 255, n, N, total,
+                              len(tail))
     h += bytes(7) + tail + bytes(8 - len(tail)) + bytes(8)
     assert len(h) == HEADER
     return h
 
 
-def compress(data: bytes, S: int, C: int, W: int, MIN: int) -> bytes:
+def compress(data: bytes, S: int, C: int, W: int, MIN: int, policy: int = 0) -> bytes:
     syms = symbols(data, S)
     m = len(syms)
     chunks = [syms[i:i + C] for i in range(0, m, C)]
     table = b""
     recs = b""
     for ch in chunks:
-        rec, F, P = record(ch, parse(ch, W, MIN), S)
+        rec, F, P = record(ch, parse(ch, W, MIN, policy), S)
         table += struct.pack("<II", F, P)
         recs += rec
     total = HEADER + len(table) + len(recs)
     tail = data[m * S:]
-    return header(len(data), S, C, W, MIN, len(chunks), total, tail) + table + recs
+    return header(len(data), S, C, W, MIN, len(chunks), total, tail, policy) + table + recs
 
 
 class Corrupt(Exception):
@@ -106,7 +133,7 @@ def tokens(stream: bytes):
     if len(stream) < HEADER or stream[:4] != b"GLZ1":
         raise Corrupt("magic")
     ver, S, pol, C, W, MIN, mx, n, N, total, r = struct.unpack_from("<HBBIHBBQQQB", stream, 4)
-    if ver != 1 or pol != 0 or mx != 255 or S not in (1, 2, 4, 8):
+    if ver != 1 or pol not in (0, 1) or mx != 255 or S not in (1, 2, 4, 8):
         raise Corrupt("header field")
     if not (1 <= C <= 1 << 24 and 1 <= W <= 256 and 1 <= MIN <= 255):
         raise Corrupt("params")

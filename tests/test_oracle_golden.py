@@ -12,7 +12,7 @@ def expected_stream(v):
     n = len(v["input"])
     S, C = v["S"], v["C"]
     N = -(-(n // S) // C)
-    hdr = refimpl.header(n, S, C, v["W"], v["MIN"], N, v["total"], v["tail"])
+    hdr = refimpl.header(n, S, C, v["W"], v["MIN"], N, v["total"], v["tail"], v["policy"])
     return hdr + v["body"]
 
 
@@ -24,7 +24,7 @@ def test_fixture_is_self_consistent(v):
 
 @pytest.mark.parametrize("v", VECTORS, ids=[v["name"] for v in VECTORS])
 def test_oracle_stream_matches_hand_vector(v):
-    got = oracle.compress(v["input"], v["S"], v["C"], v["W"], v["MIN"])
+    got = oracle.compress(v["input"], v["S"], v["C"], v["W"], v["MIN"], policy=v["policy"])
     assert got.hex() == expected_stream(v).hex()
 
 
@@ -35,7 +35,7 @@ def test_oracle_tokens_match_hand_vector(v):
     m = len(data) // S
     for i, toks in enumerate(v["tokens"]):
         chunk = data[i * C * S:min(m, (i + 1) * C) * S]
-        got = oracle.parse_chunk(chunk, S, v["W"], v["MIN"])
+        got = oracle.parse_chunk(chunk, S, v["W"], v["MIN"], policy=v["policy"])
         assert got == toks
 
 
@@ -48,5 +48,5 @@ def test_oracle_decodes_hand_vector(v):
 def test_bruteforce_reference_matches_hand_vector(v):
     if len(v["input"]) > 700:
         pytest.skip("brute force too slow")
-    got = refimpl.compress(v["input"], v["S"], v["C"], v["W"], v["MIN"])
+    got = refimpl.compress(v["input"], v["S"], v["C"], v["W"], v["MIN"], v["policy"])
     assert got.hex() == expected_stream(v).hex()

@@ -29,6 +29,14 @@ MUTANTS = {
     "tail_dropped": ("h[48 + k] = tail[k];", "h[48 + k] = 0;"),
     "decode_offset_256": ("O = pay[used + 1] ? pay[used + 1] : 256u;", "O = pay[used + 1];"),
     "decode_no_length_le_offset_check": ("|| L > O ||", "||"),
+    # match policy 1 (the paper's single window pass)
+    "scan_retries_failed_slot": ("      len = 0;\n      off = 0;\n      b = p;",
+                                 "      w -= len;\n      len = 0;\n      off = 0;\n      b = p;"),
+    "scan_drops_open_run": ("  if (len > bestL) {\n    bestL = len;\n    bestd = off;\n  }\n  *L_out",
+                            "  *L_out"),
+    "scan_ties_to_newest": ("      if (len > bestL) {", "      if (len >= bestL) {"),
+    "scan_no_255_cap": ("if (len < MAX_MATCH && sym_eq(chunk, b, w, S)) {",
+                        "if (sym_eq(chunk, b, w, S)) {"),
 }
 
 
@@ -49,8 +57,9 @@ def _pins_pass():
     for v in all_vectors():
         n = len(v["input"])
         N = -(-(n // v["S"]) // v["C"])
-        exp = refimpl.header(n, v["S"], v["C"], v["W"], v["MIN"], N, v["total"], v["tail"]) + v["body"]
-        if oracle.compress(v["input"], v["S"], v["C"], v["W"], v["MIN"]) != exp:
+        exp = refimpl.header(n, v["S"], v["C"], v["W"], v["MIN"], N, v["total"], v["tail"],
+                             v["policy"]) + v["body"]
+        if oracle.compress(v["input"], v["S"], v["C"], v["W"], v["MIN"], policy=v["policy"]) != exp:
             return False
         st, got, _ = oracle.decompress_status(exp)
         if st != oracle.OK or got != v["input"]:
@@ -80,7 +89,8 @@ def test_mutant_is_caught(name, tmp_path, monkeypatch):
     real = oracle._load()
     mlib = ctypes.CDLL(path)
     for fn in ("oracle_compress_bound", "oracle_compress", "oracle_compress_mt",
-               "oracle_decompress", "oracle_parse_chunk"):
+               "oracle_compress_policy_mt", "oracle_decompress", "oracle_parse_chunk",
+               "oracle_parse_chunk_policy"):
         getattr(mlib, fn).restype = getattr(real, fn).restype
         getattr(mlib, fn).argtypes = getattr(real, fn).argtypes
     monkeypatch.setattr(oracle, "_lib", mlib)
