@@ -12,6 +12,8 @@ window 256, minimum match 2 (seed 1).
 Other workloads (--workload), each printing its own JSON lines:
   small   1 MiB of uint16 Laplace codes (launch-latency bound): median of
           single launches and of graph replays;
+  scan    match policy 1 (the paper's single window pass) beside policy 0
+          on the field and on the 1 MiB codes;
   sweep   1 GiB per symbol width (Zipf bytes, Laplace uint16 codes, sorted
           uint32 indices, float64 field), parameters from the autotuner;
   batch   4096 buffers, log-uniform 4 KiB..64 MiB, mixed widths, one
@@ -219,6 +221,48 @@ def run_small(args):
                       "graph_replay_GBps": round(n / graph / 1e6, 3)}), flush=True)
 
 
+def run_scan(args):
+    """Match policy 1 (the paper's single window pass) against policy 0 (exact
+    longest match) on the 256 MiB field and the 1 MiB uint16 codes: GB/s and
+    ratio of each."""
+    import torch
+    from paper_2304_07342_amd import gpulz, synth
+    for key in (1, 0):
+        cfg = synth.CONFIGS[key]
+        S, C, W, MIN = cfg["S"], cfg["C"], cfg["W"], cfg["MIN"]
+        x = torch.from_numpy(cfg["make"]().view(np.uint8).reshape(-1)).to("cuda")
+        n = x.numel()
+        res = {}
+        for policy in (1, 0):
+            comp = gpulz.Compressor(n, S, C, W, MIN, policy=policy)
+            for _ in range(max(1, args.warmup)):
+                comp.compress_async(x)
+            size, status = comp.result()
+            assert status == gpulz.GPULZ_OK
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                comp.compress_async(x)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            if policy == 1 and not torch.equal(gpulz.decompress(comp.out[:size]), x):
+                raise SystemExit("round trip mismatch")
+            res[policy] = (ms, size)
+            del comp
+        print(json.dumps({
+            "metric": "compress GB/s (input) + ratio", "workload": f"{cfg['name']}-scan-policy",
+            "input_bytes": n, "symbol_bytes": S, "chunk_symbols": C, "window": W,
+            "min_match": MIN, "steps": args.steps,
+            "scan_GBps": round(n / res[1][0] / 1e6, 3), "scan_ms": round(res[1][0], 4),
+            "scan_ratio": round(n / res[1][1], 4),
+            "exact_GBps": round(n / res[0][0] / 1e6, 3), "exact_ms": round(res[0][0], 4),
+            "exact_ratio": round(n / res[0][1], 4)}), flush=True)
+        del x
+        torch.cuda.empty_cache()
+
+
 def run_batch(args):
     import torch
     from paper_2304_07342_amd import gpulz, synth
@@ -293,7 +337,7 @@ def run_batch(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="field",
-                    choices=["field", "small", "sweep", "batch", "serve"])
+                    choices=["field", "small", "scan", "sweep", "batch", "serve"])
     ap.add_argument("--sweep-bytes", type=int, default=1 << 30)
     ap.add_argument("--nbufs", type=int, default=4096)
     ap.add_argument("--pool-mib", type=int, default=256)
@@ -321,6 +365,8 @@ def main():
 
     if args.workload == "small":
         return run_small(args)
+    if args.workload == "scan":
+        return run_scan(args)
     if args.workload == "sweep":
         return run_sweep(args)
     if args.workload == "batch":

@@ -19,7 +19,7 @@
  * Stream layout (little-endian), identical for every producer:
  *   bytes 0..63   header:
  *       0  u8[4] magic "GLZ1"       4  u16 version = 1
- *       6  u8    S                  7  u8  match policy = 0 (exact longest)
+ *       6  u8    S                  7  u8  match policy: 0 exact longest, 1 single pass
  *       8  u32   C (chunk symbols) 12  u16 W (window symbols, 1..256)
  *      14  u8    min_match         15  u8  max_match = 255
  *      16  u64   n (input bytes)   24  u64 N = ceil((n / S) / C) chunks
@@ -109,6 +109,27 @@ gpulz_status gpulz_compress(const void* d_in, uint64_t nbytes, uint32_t symbol_b
                             void* d_out, uint64_t out_capacity, uint64_t* d_out_bytes,
                             int32_t* d_status, void* d_workspace, size_t ws_bytes,
                             hipStream_t stream);
+
+/* gpulz_compress with an explicit match policy, recorded in header byte 7:
+ *   0  the exact longest match (gpulz_compress);
+ *   1  the paper's own single pass over the window (gpuLZ section 3.3.2,
+ *      matching steps 1-4): per coding position, a window pointer walks once
+ *      from the oldest slot; runs of equal symbols are candidates that win
+ *      only if strictly longer; after a mismatch the look-ahead restarts at
+ *      the coding position and the walk continues at the next slot (the
+ *      failed slot is not retried as a start); the run still open when the
+ *      walk ends counts, and runs stop at 255 symbols. Lengths never exceed
+ *      offsets. Not always the longest match; cost W steps per position.
+ * Other arguments, results and errors as gpulz_compress; policy > 1 gives
+ * GPULZ_ERR_INVALID_ARG, and policy 1 also needs the chunk plus two bytes
+ * per symbol of tables in on-chip memory (GPULZ_ERR_UNSUPPORTED when
+ * C * (S + 2) exceeds about 60 KiB). Both policies decode with
+ * gpulz_decompress. */
+gpulz_status gpulz_compress_policy(const void* d_in, uint64_t nbytes, uint32_t symbol_bytes,
+                                   uint32_t chunk_symbols, uint32_t window, uint32_t min_match,
+                                   uint32_t match_policy, void* d_out, uint64_t out_capacity,
+                                   uint64_t* d_out_bytes, int32_t* d_status, void* d_workspace,
+                                   size_t ws_bytes, hipStream_t stream);
 
 /* Read the fields of a stream header from a host copy of its first 64 bytes.
  * Validates magic, version and field ranges; GPULZ_ERR_CORRUPT otherwise.

@@ -55,7 +55,7 @@ __device__ inline void parse_header(const uint8_t* h, uint64_t in_bytes, DecodeP
   bool ok = in_bytes >= kHeaderBytes;
   if (ok) {
     ok = h[0] == 'G' && h[1] == 'L' && h[2] == 'Z' && h[3] == '1' && h[4] == 1 && h[5] == 0 &&
-         h[7] == 0 && h[15] == kMaxMatch;
+         h[7] <= 1 && h[15] == kMaxMatch;  // match policy 0 or 1
     p.S = h[6];
     p.C = rd_u32(h + 8);
     p.W = (uint32_t)h[12] | ((uint32_t)h[13] << 8);

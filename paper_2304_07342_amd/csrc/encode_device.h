@@ -289,6 +289,62 @@ __device__ __forceinline__ uint32_t cand_word(const uint32_t* hits, uint32_t w, 
   return h | (h >> 1) | (next << 31);
 }
 
+// Copies the chunk HBM -> LDS with 16-byte loads (all threads); it lands
+// 16-byte aligned in LDS whatever its alignment in HBM.
+template <int S>
+__device__ __forceinline__ void stage_chunk(const ChunkJob& job, uint8_t* stage) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nbytes = job.c * S;
+  if (((uintptr_t)job.src & 15) == 0) {
+    const uint32_t nw = (nbytes + 15) / 16;
+    for (uint32_t k = tid; k < nw; k += blockDim.x) {
+      const uint64_t g = 16ull * k;
+      if (g + 16 <= job.src_avail) {
+        *reinterpret_cast<uint4*>(stage + 16 * k) = *reinterpret_cast<const uint4*>(job.src + g);
+      } else {
+        for (uint32_t b = 0; b < 16; ++b) stage[16 * k + b] = g + b < job.src_avail ? job.src[g + b] : 0;
+      }
+    }
+  } else {
+    for (uint32_t k = tid; k < nbytes; k += blockDim.x) stage[k] = job.src[k];
+  }
+}
+
+// Cursor over a candidate bitmap: 64 consecutive words cached one per lane.
+struct CandCursor {
+  uint32_t hw0, hcache;
+  __device__ __forceinline__ void init(const uint32_t* hits, uint32_t nhw, bool sampled) {
+    hw0 = 0;
+    hcache = cand_word(hits, lane_id(), nhw, sampled);
+  }
+  // First candidate at or after p (c if none); p never decreases between
+  // calls. The first look is at p's own bit in the cached words.
+  __device__ __forceinline__ uint32_t next(uint32_t p, uint32_t c, const uint32_t* hits,
+                                           uint32_t nhw, bool sampled) {
+    const uint32_t lane = lane_id();
+    const uint32_t pw = p >> 5;  // bitmap word holding position p
+    if (pw - hw0 < 64u && ((readlane(hcache, pw - hw0) >> (p & 31u)) & 1u)) return p;
+    uint32_t w = pw;
+    for (;;) {
+      if (w >= hw0 + 64) {
+        hw0 = w;
+        hcache = cand_word(hits, hw0 + lane, nhw, sampled);
+      }
+      uint32_t mine = hcache;
+      const uint32_t gw = hw0 + lane;
+      if (gw < pw) mine = 0;
+      else if (gw == pw) mine &= ~0u << (p & 31u);
+      const uint64_t nz = ballot(mine != 0);
+      if (nz) {
+        const uint32_t l = (uint32_t)__ffsll((unsigned long long)nz) - 1;
+        return min(c, (hw0 + l) * 32u + (uint32_t)__ffs(readlane(mine, l)) - 1u);
+      }
+      w = hw0 + 64;
+      if (w * 32u >= c) return c;
+    }
+  }
+};
+
 // Encodes one chunk into its scratch slot and writes {F, P} to job.sizes.
 // Every wave of the workgroup stages the chunk and builds the hit bitmap;
 // waves other than 0 return after that, wave 0 parses and encodes.
@@ -306,25 +362,9 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
   uint32_t* hits = reinterpret_cast<uint32_t*>(stage + chunk_lds_bytes(job.C, S));
   const uint32_t nhw = (uint32_t)hit_words(job.C, S);
 
-  // ---- stage: HBM -> LDS with 16-byte loads; the chunk lands 16-byte
-  // aligned in LDS whatever its alignment in HBM.
-  {
-    const uint32_t nbytes = c * S;
-    if (((uintptr_t)job.src & 15) == 0) {
-      const uint32_t nw = (nbytes + 15) / 16;
-      for (uint32_t k = tid; k < nw; k += blockDim.x) {
-        const uint64_t g = 16ull * k;
-        if (g + 16 <= job.src_avail) {
-          *reinterpret_cast<uint4*>(stage + 16 * k) = *reinterpret_cast<const uint4*>(job.src + g);
-        } else {
-          for (uint32_t b = 0; b < 16; ++b) stage[16 * k + b] = g + b < job.src_avail ? job.src[g + b] : 0;
-        }
-      }
-    } else {
-      for (uint32_t k = tid; k < nbytes; k += blockDim.x) stage[k] = job.src[k];
-    }
-    for (uint32_t k = tid; k < nhw; k += blockDim.x) hits[k] = 0;
-  }
+  // ---- stage: HBM -> LDS with 16-byte loads
+  stage_chunk<S>(job, stage);
+  for (uint32_t k = tid; k < nhw; k += blockDim.x) hits[k] = 0;
   __syncthreads();
 
   // ---- hits: all waves, one block of 64 * V positions at a time. With
@@ -361,38 +401,10 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
   uint8_t* slot = job.slot;
   uint32_t ntok = 0, pay = 0, desc = 0;
   uint32_t p = 0;
-  // 64 consecutive bitmap words cached one per lane
-  uint32_t hw0 = 0;
-  uint32_t hcache = cand_word(hits, lane, nhw, sampled);
+  CandCursor cc;
+  cc.init(hits, nhw, sampled);
   while (p < c) {
-    // next hit at or after p (first look at p's own bit in the cached words)
-    uint32_t h = c;
-    const uint32_t pw = p >> 5;  // bitmap word holding position p
-    if (pw - hw0 < 64u && ((readlane(hcache, pw - hw0) >> (p & 31u)) & 1u)) {
-      h = p;
-    } else {
-      uint32_t w = pw;
-      uint32_t first_bits = 0;
-      for (;;) {
-        if (w >= hw0 + 64) {
-          hw0 = w;
-          hcache = cand_word(hits, hw0 + lane, nhw, sampled);
-        }
-        uint32_t mine = hcache;
-        const uint32_t gw = hw0 + lane;
-        if (gw < pw) mine = 0;
-        else if (gw == pw) mine &= ~0u << (p & 31u);
-        const uint64_t nz = ballot(mine != 0);
-        if (nz) {
-          const uint32_t l = (uint32_t)__ffsll((unsigned long long)nz) - 1;
-          first_bits = readlane(mine, l);
-          h = min(c, (hw0 + l) * 32u + (uint32_t)__ffs(first_bits) - 1u);
-          break;
-        }
-        w = hw0 + 64;
-        if (w * 32u >= c) break;
-      }
-    }
+    const uint32_t h = cc.next(p, c, hits, nhw, sampled);
     // literals for [p, h)
     while (p < h) {
       const uint32_t sl = ntok & 63u;
@@ -508,6 +520,108 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
     if (lane == (ntok & 63u)) desc = val;
     ++ntok;
     if ((ntok & 63u) == 0) encode_group<S>(64, desc, (ntok >> 6) - 1, win, slot, job.flag_area, pay);
+  }
+  if (ntok & 63u) encode_group<S>(ntok & 63u, desc, ntok >> 6, win, slot, job.flag_area, pay);
+  if (lane == 0) {
+    job.sizes[0] = (ntok + 7) / 8;
+    job.sizes[1] = pay;
+  }
+}
+
+// ---- match policy 1: the paper's single window pass ----------------------
+
+// LDS of one policy-1 chunk encoder: chunk | lengths (u8) | offsets - 1 (u8)
+// | candidate bitmap.
+__host__ __device__ constexpr uint64_t scan_lds_bytes(uint32_t C, uint32_t S) {
+  return chunk_lds_bytes(C, S) + 2 * align_up(C, 16) + 4 * hit_words(C, S);
+}
+
+// Encodes one chunk with match policy 1 (section 3.3.2, matching steps 1-4,
+// Kernel I): every position gets the result of its own single pass over
+// the window, one position per lane (the walk takes min(W, p) steps at
+// every position, so the lanes stay in step), stored as a length / offset
+// table; positions whose length reaches MIN form the candidate bitmap. Wave
+// 0 then parses greedily as on the exact path, taking each pointer from the
+// table. Per position: a window pointer w walks once from the oldest slot
+// toward p and a look-ahead pointer b from p; equal symbols extend the
+// open run (its offset is p - w at its first symbol); at a mismatch, or
+// once the run has 255 symbols, the run replaces the best one if strictly
+// longer, b returns to p, and w moves on; the walk ends when w reaches p or
+// b the chunk end, and the open run is compared once more.
+template <int S>
+__device__ void encode_chunk_scan(const ChunkJob& job, uint8_t* lds) {
+  using T = typename SymType<S>::T;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = tid >> 6;
+  const uint32_t nwaves = blockDim.x >> 6;
+  const uint32_t c = job.c;
+  uint8_t* stage = lds;
+  uint8_t* Ltab = stage + chunk_lds_bytes(job.C, S);
+  uint8_t* Dtab = Ltab + align_up(job.C, 16);
+  uint32_t* hits = reinterpret_cast<uint32_t*>(Dtab + align_up(job.C, 16));
+  const uint32_t nhw = (uint32_t)hit_words(job.C, S);
+
+  stage_chunk<S>(job, stage);
+  for (uint32_t k = tid; k < nhw; k += blockDim.x) hits[k] = 0;
+  __syncthreads();
+  const T* win = reinterpret_cast<const T*>(stage);
+
+  // ---- per-position walks, 64 consecutive positions per wave
+  for (uint32_t base = 64 * wave; base < c; base += 64 * nwaves) {
+    const uint32_t p = base + lane;
+    uint32_t bestL = 0, bestd = 0;
+    if (p < c) {
+      uint32_t w = p > job.W ? p - job.W : 0, b = p, len = 0, off = 0;
+      while (w < p && b < c) {
+        const bool eq = (len < kMaxMatch) & (win[b] == win[w]);
+        off = eq & (len == 0) ? p - w : off;
+        const bool better = !eq & (len > bestL);
+        bestL = better ? len : bestL;
+        bestd = better ? off : bestd;
+        len = eq ? len + 1 : 0u;
+        b = eq ? b + 1 : p;
+        ++w;
+      }
+      if (len > bestL) {
+        bestL = len;
+        bestd = off;
+      }
+      Ltab[p] = (uint8_t)bestL;
+      Dtab[p] = (uint8_t)(bestd - 1);
+    }
+    const uint64_t m = ballot(p < c && bestL >= job.MIN);
+    if (lane == 0) {
+      hits[base >> 5] = (uint32_t)m;
+      hits[(base >> 5) + 1] = (uint32_t)(m >> 32);
+    }
+  }
+  __syncthreads();
+  if (wave != 0) return;
+
+  // ---- greedy parse + encode (wave 0): candidates are exactly the
+  // positions whose walk found a run of at least MIN symbols
+  uint8_t* slot = job.slot;
+  uint32_t ntok = 0, pay = 0, desc = 0;
+  uint32_t p = 0;
+  CandCursor cc;
+  cc.init(hits, nhw, false);
+  while (p < c) {
+    const uint32_t h = cc.next(p, c, hits, nhw, false);
+    while (p < h) {
+      const uint32_t sl = ntok & 63u;
+      const uint32_t take = min(h - p, 64u - sl);
+      if (lane >= sl && lane < sl + take) desc = (p + lane - sl) << 1;
+      ntok += take;
+      p += take;
+      if ((ntok & 63u) == 0) encode_group<S>(64, desc, (ntok >> 6) - 1, win, slot, job.flag_area, pay);
+    }
+    if (h >= c) break;
+    const uint32_t L = Ltab[h], d = (uint32_t)Dtab[h] + 1u;
+    if (lane == (ntok & 63u)) desc = 1u | (L << 1) | ((d & 0xFFu) << 9);
+    ++ntok;
+    if ((ntok & 63u) == 0) encode_group<S>(64, desc, (ntok >> 6) - 1, win, slot, job.flag_area, pay);
+    p = h + L;
   }
   if (ntok & 63u) encode_group<S>(ntok & 63u, desc, ntok >> 6, win, slot, job.flag_area, pay);
   if (lane == 0) {

@@ -169,14 +169,16 @@ gpulz_status gpulz_compress_workspace_size(uint64_t nbytes, uint32_t S, uint32_t
   return GPULZ_OK;
 }
 
-gpulz_status gpulz_compress(const void* d_in, uint64_t nbytes, uint32_t S, uint32_t C, uint32_t W,
-                            uint32_t MIN, void* d_out, uint64_t out_capacity, uint64_t* d_out_bytes,
-                            int32_t* d_status, void* d_ws, size_t ws_bytes, hipStream_t stream) {
-  if (!valid_params(S, C, W, MIN)) return GPULZ_ERR_INVALID_ARG;
+gpulz_status gpulz_compress_policy(const void* d_in, uint64_t nbytes, uint32_t S, uint32_t C,
+                                   uint32_t W, uint32_t MIN, uint32_t policy, void* d_out,
+                                   uint64_t out_capacity, uint64_t* d_out_bytes, int32_t* d_status,
+                                   void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  if (!valid_params(S, C, W, MIN) || policy > 1) return GPULZ_ERR_INVALID_ARG;
   if ((nbytes && !d_in) || !d_out_bytes || !d_status || (out_capacity && !d_out))
     return GPULZ_ERR_INVALID_ARG;
   if (!aligned(d_in, 16) || !aligned(d_out, 16) || !aligned(d_ws, 256)) return GPULZ_ERR_INVALID_ARG;
   if ((uint64_t)C * S > kMaxChunkBytes) return GPULZ_ERR_UNSUPPORTED;
+  if (policy == 1 && encode_scan_lds_bytes(C, S) > kMaxGroupLdsBytes) return GPULZ_ERR_UNSUPPORTED;
   const uint64_t N = num_chunks(nbytes, S, C);
   const CompressWorkspace w = compress_workspace(N, C, S, 1);
   if (!d_ws || ws_bytes < w.total) return GPULZ_ERR_WORKSPACE;
@@ -200,7 +202,9 @@ gpulz_status gpulz_compress(const void* d_in, uint64_t nbytes, uint32_t S, uint3
     waves = g_defaults[width_index(S)].waves_per_chunk;
   }
   int pi = prof_begin(0, stream);
-  if (launch_encode(e, S, N, waves, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  const hipError_t le = policy == 0 ? launch_encode(e, S, N, waves, stream)
+                                    : launch_encode_scan(e, S, N, waves, stream);
+  if (le != hipSuccess) return GPULZ_ERR_HIP;
   prof_end(pi, stream);
 
   ScanArgs sa;
@@ -213,6 +217,7 @@ gpulz_status gpulz_compress(const void* d_in, uint64_t nbytes, uint32_t S, uint3
   sa.C = C;
   sa.W = W;
   sa.MIN = MIN;
+  sa.policy = policy;
   sa.out = static_cast<uint8_t*>(d_out);
   sa.capacity = out_capacity;
   sa.out_bytes = d_out_bytes;
@@ -236,6 +241,13 @@ gpulz_status gpulz_compress(const void* d_in, uint64_t nbytes, uint32_t S, uint3
   return GPULZ_OK;
 }
 
+gpulz_status gpulz_compress(const void* d_in, uint64_t nbytes, uint32_t S, uint32_t C, uint32_t W,
+                            uint32_t MIN, void* d_out, uint64_t out_capacity, uint64_t* d_out_bytes,
+                            int32_t* d_status, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  return gpulz_compress_policy(d_in, nbytes, S, C, W, MIN, 0, d_out, out_capacity, d_out_bytes,
+                               d_status, d_ws, ws_bytes, stream);
+}
+
 gpulz_status gpulz_peek_header(const void* h_header, size_t header_bytes, uint64_t* nbytes,
                                uint32_t* symbol_bytes, uint64_t* stream_bytes) {
   if (!h_header || header_bytes < kHeaderBytes) return GPULZ_ERR_INVALID_ARG;
@@ -247,7 +259,7 @@ gpulz_status gpulz_peek_header(const void* h_header, size_t header_bytes, uint64
   for (int k = 7; k >= 0; --k) total = (total << 8) | h[32 + k];
   for (int k = 3; k >= 0; --k) C = (C << 8) | h[8 + k];
   const uint32_t W = (uint32_t)h[12] | ((uint32_t)h[13] << 8);
-  if (!valid_params(h[6], C, W, h[14]) || h[7] != 0 || h[15] != kMaxMatch) return GPULZ_ERR_CORRUPT;
+  if (!valid_params(h[6], C, W, h[14]) || h[7] > 1 || h[15] != kMaxMatch) return GPULZ_ERR_CORRUPT;
   if (nbytes) *nbytes = n;
   if (symbol_bytes) *symbol_bytes = h[6];
   if (stream_bytes) *stream_bytes = total;

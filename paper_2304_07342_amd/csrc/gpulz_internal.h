@@ -14,6 +14,7 @@ constexpr uint32_t kMaxWindow = 256;
 constexpr uint32_t kMaxChunkBytes = 48 * 1024;
 // Per-wave LDS ring the decoder rebuilds symbols in (independent of C).
 constexpr uint32_t kDecodeRingBytes = 16 * 1024;
+constexpr uint64_t kMaxGroupLdsBytes = 64 * 1024;  // LDS one workgroup may allocate
 
 // Device status values (same numbering as gpulz_status).
 enum : int32_t { kOk = 0, kInvalidArg = 1, kOutOfSpace = 2, kCorrupt = 3, kWorkspace = 4 };
@@ -68,7 +69,7 @@ struct ScanArgs {
   uint64_t* offsets;    // N + 1 entries (exclusive prefix, then the sum)
   const uint8_t* in;    // for the tail bytes
   uint64_t nbytes;
-  uint32_t S, C, W, MIN;
+  uint32_t S, C, W, MIN, policy;
   uint8_t* out;
   uint64_t capacity;
   uint64_t* out_bytes;
@@ -91,6 +92,9 @@ hipError_t launch_encode(const EncodeArgs& a, uint32_t S, uint64_t N, uint32_t w
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
 size_t encode_lds_bytes(uint32_t C, uint32_t S, uint32_t W);
+size_t encode_scan_lds_bytes(uint32_t C, uint32_t S);
+hipError_t launch_encode_scan(const EncodeArgs& a, uint32_t S, uint64_t N, uint32_t waves,
+                              hipStream_t s);
 
 // ---- decompress -------------------------------------------------------------
 

@@ -1,5 +1,6 @@
-// Single-buffer chunk encoder kernel: one workgroup of 1, 2 or 4 wavefronts
-// per chunk (see encode_device.h for the steps).
+// Single-buffer chunk encoder kernels: one workgroup of 1, 2 or 4 wavefronts
+// per chunk (see encode_device.h for the steps), for match policy 0 (exact
+// longest match) and 1 (the paper's single window pass).
 #include "encode_device.h"
 
 namespace gpulz {
@@ -39,7 +40,46 @@ hipError_t launch_s(const EncodeArgs& a, uint64_t N, uint32_t waves, hipStream_t
   }
 }
 
+// Policy-1 chunk encoder kernel: one workgroup per chunk.
+template <int S>
+__global__ __launch_bounds__(64 * enc::kEncodeWaves) void encode_scan_kernel(EncodeArgs a) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const uint64_t chunk = blockIdx.x;
+  const uint64_t cs = chunk * a.C;
+  enc::ChunkJob job;
+  job.src = a.in + cs * S;
+  job.src_avail = a.nbytes - cs * S;
+  job.c = (uint32_t)min<uint64_t>(a.C, a.m - cs);
+  job.C = a.C;
+  job.W = a.W;
+  job.MIN = a.MIN;
+  job.slot = a.slots + chunk * a.slot_bytes;
+  job.flag_area = a.flag_area;
+  job.sizes = a.sizes + 2 * chunk;
+  enc::encode_chunk_scan<S>(job, lds);
+}
+
+template <int S>
+hipError_t launch_scan_s(const EncodeArgs& a, uint64_t N, uint32_t waves, hipStream_t s) {
+  const size_t lds = enc::scan_lds_bytes(a.C, S);
+  hipLaunchKernelGGL((encode_scan_kernel<S>), dim3((uint32_t)N), dim3(64 * waves), lds, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+size_t encode_scan_lds_bytes(uint32_t C, uint32_t S) { return enc::scan_lds_bytes(C, S); }
+
+hipError_t launch_encode_scan(const EncodeArgs& a, uint32_t S, uint64_t N, uint32_t waves,
+                              hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  switch (S) {
+    case 1: return launch_scan_s<1>(a, N, waves, s);
+    case 2: return launch_scan_s<2>(a, N, waves, s);
+    case 4: return launch_scan_s<4>(a, N, waves, s);
+    default: return launch_scan_s<8>(a, N, waves, s);
+  }
+}
 
 size_t encode_lds_bytes(uint32_t C, uint32_t S, uint32_t W) {
   return enc::encode_lds(C, S, (W + 63) / 64);

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(ScanArgs a) {
     *a.status = total <= a.capacity ? kOk : kOutOfSpace;
   }
   if (total <= a.capacity && tid < kHeaderBytes)
-    a.out[tid] = stream::header_byte(tid, a.nbytes, a.S, a.C, a.W, a.MIN, a.N, total, a.in);
+    a.out[tid] = stream::header_byte(tid, a.nbytes, a.S, a.C, a.W, a.MIN, a.policy, a.N, total, a.in);
 }
 
 __global__ __launch_bounds__(256) void scatter_kernel(ScatterArgs a) {

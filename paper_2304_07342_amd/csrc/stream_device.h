@@ -9,7 +9,7 @@ namespace stream {
 
 // Byte b (0..63) of the stream header.
 __device__ inline uint8_t header_byte(uint32_t b, uint64_t n, uint32_t S, uint32_t C, uint32_t W,
-                                      uint32_t MIN, uint64_t N, uint64_t total,
+                                      uint32_t MIN, uint32_t policy, uint64_t N, uint64_t total,
                                       const uint8_t* in) {
   const uint32_t r = (uint32_t)(n % S);
   switch (b) {
@@ -19,6 +19,7 @@ __device__ inline uint8_t header_byte(uint32_t b, uint64_t n, uint32_t S, uint32
     case 3: return '1';
     case 4: return 1;  // version
     case 6: return (uint8_t)S;
+    case 7: return (uint8_t)policy;  // match policy
     case 14: return (uint8_t)MIN;
     case 15: return (uint8_t)kMaxMatch;
     case 40: return (uint8_t)r;

@@ -25,7 +25,7 @@ GPULZ_ERR_UNSUPPORTED = 6
 # Every symbol the C header declares.
 EXPORTS = (
     "gpulz_abi_version", "gpulz_status_string", "gpulz_compress_bound",
-    "gpulz_compress_workspace_size", "gpulz_compress", "gpulz_peek_header",
+    "gpulz_compress_workspace_size", "gpulz_compress", "gpulz_compress_policy", "gpulz_peek_header",
     "gpulz_decompress_workspace_size", "gpulz_decompress", "gpulz_default_params",
     "gpulz_set_default_params", "gpulz_compress_batch_workspace_size", "gpulz_compress_batch",
     "gpulz_decompress_batch_workspace_size", "gpulz_decompress_batch", "gpulz_profile_enable",
@@ -82,6 +82,9 @@ def lib() -> ctypes.CDLL:
         L.gpulz_compress_workspace_size.argtypes = [u64, u32, u32, ctypes.POINTER(sz)]
         L.gpulz_compress.restype = ctypes.c_int
         L.gpulz_compress.argtypes = [vp, u64, u32, u32, u32, u32, vp, u64, vp, vp, vp, sz, vp]
+        L.gpulz_compress_policy.restype = ctypes.c_int
+        L.gpulz_compress_policy.argtypes = [vp, u64, u32, u32, u32, u32, u32, vp, u64, vp, vp, vp,
+                                            sz, vp]
         L.gpulz_peek_header.restype = ctypes.c_int
         L.gpulz_peek_header.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(u64),
                                         ctypes.POINTER(u32), ctypes.POINTER(u64)]
@@ -142,6 +145,15 @@ def gpulz_compress(d_in: int, nbytes: int, symbol_bytes: int, chunk_symbols: int
                    d_workspace: int, ws_bytes: int, stream: int = 0) -> int:
     return lib().gpulz_compress(d_in, nbytes, symbol_bytes, chunk_symbols, window, min_match, d_out,
                                 out_capacity, d_out_bytes, d_status, d_workspace, ws_bytes, stream)
+
+
+def gpulz_compress_policy(d_in: int, nbytes: int, symbol_bytes: int, chunk_symbols: int,
+                          window: int, min_match: int, match_policy: int, d_out: int,
+                          out_capacity: int, d_out_bytes: int, d_status: int, d_workspace: int,
+                          ws_bytes: int, stream: int = 0) -> int:
+    return lib().gpulz_compress_policy(d_in, nbytes, symbol_bytes, chunk_symbols, window,
+                                       min_match, match_policy, d_out, out_capacity, d_out_bytes,
+                                       d_status, d_workspace, ws_bytes, stream)
 
 
 def gpulz_peek_header(header: bytes):
@@ -249,9 +261,10 @@ class Compressor:
     back the size and status (synchronising the stream)."""
 
     def __init__(self, max_bytes: int, symbol_bytes: int, chunk_symbols: int, window: int,
-                 min_match: int, device="cuda"):
+                 min_match: int, device="cuda", policy: int = 0):
         torch = _torch()
         self.S, self.C, self.W, self.MIN = symbol_bytes, chunk_symbols, window, min_match
+        self.policy = policy
         self.capacity = gpulz_compress_bound(max_bytes, symbol_bytes, chunk_symbols, min_match)
         if self.capacity == 0:
             raise GpulzError(GPULZ_ERR_INVALID_ARG, "gpulz_compress_bound")
@@ -262,11 +275,11 @@ class Compressor:
 
     def compress_async(self, x, nbytes: int | None = None, stream=None) -> None:
         nbytes = x.numel() * x.element_size() if nbytes is None else nbytes
-        st = gpulz_compress(x.data_ptr(), nbytes, self.S, self.C, self.W, self.MIN,
-                            self.out.data_ptr(), self.capacity, self.meta.data_ptr(),
-                            self.meta.data_ptr() + 8, self.ws.data_ptr(), self.ws_bytes,
-                            _stream_handle(stream))
-        _check(st, "gpulz_compress")
+        st = gpulz_compress_policy(x.data_ptr(), nbytes, self.S, self.C, self.W, self.MIN,
+                                   self.policy, self.out.data_ptr(), self.capacity,
+                                   self.meta.data_ptr(), self.meta.data_ptr() + 8,
+                                   self.ws.data_ptr(), self.ws_bytes, _stream_handle(stream))
+        _check(st, "gpulz_compress_policy")
 
     def result(self):
         """(stream bytes, device status)."""
@@ -274,10 +287,13 @@ class Compressor:
         return int(meta[0]), int(meta[1]) & 0xFFFFFFFF
 
 
-def compress(x, symbol_bytes: int, chunk_symbols: int, window: int, min_match: int, stream=None):
-    """Compress a device tensor's bytes; returns a uint8 device tensor."""
+def compress(x, symbol_bytes: int, chunk_symbols: int, window: int, min_match: int, stream=None,
+             policy: int = 0):
+    """Compress a device tensor's bytes; returns a uint8 device tensor.
+    policy 0 = exact longest match, 1 = the paper's single window pass."""
     nbytes = x.numel() * x.element_size()
-    c = Compressor(max(nbytes, 1), symbol_bytes, chunk_symbols, window, min_match, device=x.device)
+    c = Compressor(max(nbytes, 1), symbol_bytes, chunk_symbols, window, min_match, device=x.device,
+                   policy=policy)
     c.compress_async(x, nbytes, stream)
     size, status = c.result()
     _check(status, "gpulz_compress (device status)")

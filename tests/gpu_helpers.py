@@ -17,7 +17,7 @@ def to_device(x: np.ndarray):
     return t
 
 
-def gpu_compress(x, S, C, W, MIN, capacity=None, slack=64):
+def gpu_compress(x, S, C, W, MIN, capacity=None, slack=64, policy=0):
     """Run gpulz_compress; returns (status, stream bytes or None, out_bytes,
     canary_intact). The output buffer has `slack` canary bytes past the
     capacity to detect writes beyond it."""
@@ -32,9 +32,15 @@ def gpu_compress(x, S, C, W, MIN, capacity=None, slack=64):
     ws_bytes = gpulz.gpulz_compress_workspace_size(n, S, C)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     meta = torch.zeros(2, dtype=torch.int64, device="cuda")
-    st = gpulz.gpulz_compress(d_in.data_ptr(), n, S, C, W, MIN, out.data_ptr(), cap,
-                              meta.data_ptr(), meta.data_ptr() + 8, ws.data_ptr(), ws_bytes,
-                              torch.cuda.current_stream().cuda_stream)
+    stream = torch.cuda.current_stream().cuda_stream
+    if policy == 0:
+        st = gpulz.gpulz_compress(d_in.data_ptr(), n, S, C, W, MIN, out.data_ptr(), cap,
+                                  meta.data_ptr(), meta.data_ptr() + 8, ws.data_ptr(), ws_bytes,
+                                  stream)
+    else:
+        st = gpulz.gpulz_compress_policy(d_in.data_ptr(), n, S, C, W, MIN, policy, out.data_ptr(),
+                                         cap, meta.data_ptr(), meta.data_ptr() + 8, ws.data_ptr(),
+                                         ws_bytes, stream)
     assert st == gpulz.GPULZ_OK, gpulz.status_string(st)
     torch.cuda.synchronize()
     m = meta.cpu().numpy()

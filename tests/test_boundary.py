@@ -84,6 +84,23 @@ def test_compress_rejects_bad_parameters(S, C, W, MIN, code):
     assert st == code
 
 
+def test_compress_policy_rejects_before_any_launch():
+    # every case fails host validation, so the fake pointers are never used
+    ws = 1 << 30
+    st = gpulz.gpulz_compress_policy(FAKE, 4096, 2, 64, 16, 2, 2, FAKE, 1 << 20, FAKE, FAKE, FAKE, ws)
+    assert st == gpulz.GPULZ_ERR_INVALID_ARG  # no policy 2
+    st = gpulz.gpulz_compress_policy(FAKE, 4096, 3, 64, 16, 2, 1, FAKE, 1 << 20, FAKE, FAKE, FAKE, ws)
+    assert st == gpulz.GPULZ_ERR_INVALID_ARG
+    # policy 1 keeps two table bytes per symbol in on-chip memory
+    st = gpulz.gpulz_compress_policy(FAKE, 1 << 20, 1, 40000, 16, 2, 1, FAKE, 1 << 22, FAKE, FAKE,
+                                     FAKE, ws)
+    assert st == gpulz.GPULZ_ERR_UNSUPPORTED
+    need = gpulz.gpulz_compress_workspace_size(4096, 2, 64)
+    st = gpulz.gpulz_compress_policy(FAKE, 4096, 2, 64, 16, 2, 1, FAKE, 1 << 20, FAKE, FAKE, FAKE,
+                                     need - 1)
+    assert st == gpulz.GPULZ_ERR_WORKSPACE
+
+
 def test_compress_rejects_misaligned_and_null_pointers():
     args = dict(S=2, C=64, W=16, MIN=2)
     st = gpulz.gpulz_compress(FAKE + 4, 4096, 2, 64, 16, 2, FAKE, 1 << 20, FAKE, FAKE, FAKE, 1 << 30)
