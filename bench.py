@@ -14,6 +14,8 @@ Other workloads (--workload), each printing its own JSON lines:
           single launches and of graph replays;
   scan    match policy 1 (the paper's single window pass) beside policy 0
           on the field and on the 1 MiB codes;
+  adaptive  the adaptive symbol width / window rule and its levels on each
+          content kind, against the element-width default;
   sweep   1 GiB per symbol width (Zipf bytes, Laplace uint16 codes, sorted
           uint32 indices, float64 field), parameters from the autotuner;
   batch   4096 buffers, log-uniform 4 KiB..64 MiB, mixed widths, one
@@ -263,6 +265,53 @@ def run_scan(args):
         torch.cuda.empty_cache()
 
 
+def run_adaptive(args):
+    """Section 3.2.3's adaptive width / window rule on each content kind
+    (256 MiB, four 64 MiB fields): the element-width default against the
+    adaptive plan at each level; GB/s and ratio of each."""
+    import torch
+    from paper_2304_07342_amd import adaptive, gpulz, synth
+    kinds = {"zipf-u8": 1, "laplace-u16": 2, "sorted-u32": 4, "field-f32": 4, "field-f64": 8}
+    size = args.pool_mib << 20
+    for i, (kind, E) in enumerate(kinds.items()):
+        x = torch.from_numpy(synth.POOL_KINDS[kind][1](size, 300 + i)[:size]).to("cuda")
+        fields = list(x.split(size // 4))
+        out = {"metric": "compress GB/s (input) + ratio", "workload": f"adaptive-{kind}",
+               "input_bytes": size, "element_bytes": E, "runs": []}
+
+        def timed(S, C, W, MIN):
+            comp = gpulz.Compressor(size, S, C, W, MIN)
+            comp.compress_async(x)
+            nbytes, st = comp.result()
+            assert st == gpulz.GPULZ_OK
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            stream = torch.cuda.current_stream()
+            e0.record(stream)
+            for _ in range(3):
+                comp.compress_async(x)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 3
+            return round(size / ms / 1e6, 3), round(size / nbytes, 4)
+
+        C, W, MIN, _ = gpulz.gpulz_default_params(E)
+        gbps, ratio = timed(E, C, W, MIN)
+        out["runs"].append({"plan": "element width, default window", "S": E, "C": C, "W": W,
+                            "GBps": gbps, "ratio": ratio})
+        for level in (1, 2, 3, 4):
+            p = adaptive.plan(fields, E, level)
+            gbps, ratio = timed(p.symbol_bytes, p.chunk_symbols, p.window, p.min_match)
+            out["runs"].append({"plan": f"adaptive level {level}", "S": p.symbol_bytes,
+                                "C": p.chunk_symbols, "W": p.window,
+                                "multi_byte_ratio": None if p.multi_byte_ratio is None
+                                else round(p.multi_byte_ratio, 4),
+                                "GBps": gbps, "ratio": ratio})
+            log(f"adaptive {kind} level {level}: S={p.symbol_bytes} W={p.window} {gbps} GB/s r{ratio}")
+        print(json.dumps(out), flush=True)
+        del x, fields
+        torch.cuda.empty_cache()
+
+
 def run_batch(args):
     import torch
     from paper_2304_07342_amd import gpulz, synth
@@ -337,7 +386,7 @@ def run_batch(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="field",
-                    choices=["field", "small", "scan", "sweep", "batch", "serve"])
+                    choices=["field", "small", "scan", "sweep", "adaptive", "batch", "serve"])
     ap.add_argument("--sweep-bytes", type=int, default=1 << 30)
     ap.add_argument("--nbufs", type=int, default=4096)
     ap.add_argument("--pool-mib", type=int, default=256)
@@ -367,6 +416,8 @@ def main():
         return run_small(args)
     if args.workload == "scan":
         return run_scan(args)
+    if args.workload == "adaptive":
+        return run_adaptive(args)
     if args.workload == "sweep":
         return run_sweep(args)
     if args.workload == "batch":
