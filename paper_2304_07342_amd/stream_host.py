@@ -10,25 +10,35 @@ whole input at once.
 
 Pipeline (two device buffer sets, three streams): the host-to-device copy of
 block k + 1 overlaps the compression of block k and the device-to-host copies
-of block k - 1; pinned host staging keeps the copies asynchronous.
+of block k - 1. Pageable input is staged into pinned buffers by a pool of
+host threads (a pinned torch input is copied from directly); the output
+stream is allocated pinned, so the device-to-host copies land in their final
+places with no second host copy.
 Decompression streams the same way: each block of chunks becomes a small
 standalone stream (its own header, its slice of the table and its records)
-that is decoded on the device and copied back.
+that is decoded on the device and copied into the pinned output.
 """
 from __future__ import annotations
 
+import os
 import struct
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
 from . import gpulz
 
 HEADER = 64
+_COPY_PIECE = 8 << 20
 
 
 def default_block_bytes(fraction: float = 0.30) -> int:
     import torch
     return int(torch.cuda.get_device_properties(0).total_memory * fraction)
+
+
+def default_threads() -> int:
+    return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 def block_plan(nbytes: int, S: int, C: int, block_bytes: int):
@@ -57,82 +67,133 @@ def header(n: int, S: int, C: int, W: int, MIN: int, policy: int, N: int, total:
     return h + bytes(7) + tail + bytes(8 - len(tail)) + bytes(8)
 
 
-def compress_host(x: np.ndarray, S: int, C: int, W: int, MIN: int, policy: int = 0,
-                  block_bytes: int | None = None) -> np.ndarray:
-    """Compress a host array (any dtype; its bytes) into one stream (a host
-    uint8 array)."""
+def _host_bytes(x):
+    """(uint8 numpy view, pinned torch uint8 view or None) of a host array or
+    CPU tensor."""
     import torch
-    src = np.ascontiguousarray(x).view(np.uint8).reshape(-1)
+    if isinstance(x, torch.Tensor):
+        if x.device.type != "cpu":
+            raise ValueError("host streaming takes a host array or CPU tensor")
+        t = x.contiguous().view(-1).view(torch.uint8)
+        return t.numpy(), (t if t.is_pinned() else None)
+    return np.ascontiguousarray(x).view(np.uint8).reshape(-1), None
+
+
+class _Copier:
+    """Host memcpy split over a thread pool (numpy releases the GIL while it
+    copies)."""
+
+    def __init__(self, threads: int):
+        self.pool = ThreadPoolExecutor(threads) if threads > 1 else None
+
+    def __call__(self, dst: np.ndarray, src: np.ndarray) -> None:
+        n = src.size
+        if self.pool is None or n <= _COPY_PIECE:
+            dst[:n] = src
+            return
+        futs = [self.pool.submit(np.copyto, dst[a:min(n, a + _COPY_PIECE)],
+                                 src[a:min(n, a + _COPY_PIECE)])
+                for a in range(0, n, _COPY_PIECE)]
+        for f in futs:
+            f.result()
+
+    def close(self):
+        if self.pool is not None:
+            self.pool.shutdown()
+
+
+def compress_host(x, S: int, C: int, W: int, MIN: int, policy: int = 0,
+                  block_bytes: int | None = None, threads: int | None = None) -> np.ndarray:
+    """Compress a host array or CPU tensor (its bytes) into one stream,
+    returned as a uint8 numpy array over pinned host memory."""
+    import torch
+    src, src_pinned = _host_bytes(x)
     n = src.size
     block_bytes = block_bytes or default_block_bytes()
     blocks = block_plan(n, S, C, block_bytes)
     N = -(-(n // S) // C)
     cap = gpulz.gpulz_compress_bound(n, S, C, MIN)
-    out = np.empty(cap, dtype=np.uint8)
-    bmax = max(b for _, b, _, _ in blocks)
-    dev = [torch.empty(max(bmax, 1), dtype=torch.uint8, device="cuda") for _ in range(2)]
-    pin = [torch.empty(max(bmax, 1), dtype=torch.uint8).pin_memory() for _ in range(2)]
-    comps = [gpulz.Compressor(max(bmax, 1), S, C, W, MIN, policy=policy) for _ in range(2)]
+    if cap == 0:
+        raise gpulz.GpulzError(gpulz.GPULZ_ERR_INVALID_ARG, "gpulz_compress_bound")
+    out_t = torch.empty(cap, dtype=torch.uint8, pin_memory=True)
+    bmax = max(1, max(b for _, b, _, _ in blocks))
+    dev = [torch.empty(bmax, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    pin = None if src_pinned is not None else \
+        [torch.empty(bmax, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
+    comps = [gpulz.Compressor(bmax, S, C, W, MIN, policy=policy) for _ in range(2)]
     copy_in, work, copy_out = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
-    loaded = [torch.cuda.Event() for _ in range(2)]
-    done = [torch.cuda.Event() for _ in range(2)]
-    freed = [torch.cuda.Event() for _ in range(2)]
-    pend = []
+    loaded = [torch.cuda.Event() for _ in range(2)]   # host-to-device copy of the block done
+    done = [torch.cuda.Event() for _ in range(2)]     # its compression done
+    copied = [torch.cuda.Event() for _ in range(2)]   # its stream copied back
+    used = [False, False]
+    copier = _Copier(threads or default_threads())
     rec_off = HEADER + 8 * N
 
     def stage(k):
         off, nb, _, _ = blocks[k]
         j = k % 2
-        freed[j].synchronize()  # the pinned buffer and device buffer are free again
-        pin[j][:nb].numpy()[:] = src[off:off + nb]
+        if used[j]:
+            loaded[j].synchronize()            # the pinned staging buffer is free again
+            copy_in.wait_event(done[j])        # the device buffer is free again
+        if pin is None:
+            host = src_pinned[off:off + nb]
+        else:
+            copier(pin[j].numpy(), src[off:off + nb])
+            host = pin[j][:nb]
         with torch.cuda.stream(copy_in):
-            dev[j][:nb].copy_(pin[j][:nb], non_blocking=True)
+            dev[j][:nb].copy_(host, non_blocking=True)
             loaded[j].record(copy_in)
+
+    def compress(k):
+        _, nb, _, _ = blocks[k]
+        j = k % 2
+        work.wait_event(loaded[j])
+        if used[j]:
+            work.wait_event(copied[j])         # the previous stream in this buffer is copied out
+        comps[j].compress_async(dev[j][:nb], nb, stream=work)
+        done[j].record(work)
+        used[j] = True
 
     def drain(k):
         nonlocal rec_off
         j = k % 2
-        _, nb, c0, nc = blocks[k]
+        _, _, c0, nc = blocks[k]
         done[j].synchronize()
         size, status = comps[j].result()
         if status != gpulz.GPULZ_OK:
             raise gpulz.GpulzError(status, "block compress")
-        with torch.cuda.stream(copy_out):
-            body = comps[j].out[HEADER:size].cpu()
-            freed[j].record(copy_out)
-        b = body.numpy()
-        out[HEADER + 8 * c0:HEADER + 8 * (c0 + nc)] = b[:8 * nc]
         rec = size - HEADER - 8 * nc
-        out[rec_off:rec_off + rec] = b[8 * nc:]
+        body = comps[j].out
+        with torch.cuda.stream(copy_out):
+            out_t[HEADER + 8 * c0:HEADER + 8 * (c0 + nc)].copy_(body[HEADER:HEADER + 8 * nc],
+                                                               non_blocking=True)
+            out_t[rec_off:rec_off + rec].copy_(body[HEADER + 8 * nc:size], non_blocking=True)
+            copied[j].record(copy_out)
         rec_off += rec
 
-    for j in range(2):
-        freed[j].record(torch.cuda.current_stream())
-    if blocks:
+    try:
         stage(0)
-    for k in range(len(blocks)):
-        j = k % 2
-        _, nb, _, _ = blocks[k]
-        with torch.cuda.stream(work):
-            work.wait_event(loaded[j])
-            comps[j].compress_async(dev[j][:nb], nb, stream=work)
-            done[j].record(work)
-        if k + 1 < len(blocks):
-            if pend:
-                drain(pend.pop(0))
-            stage(k + 1)
-        pend.append(k)
-    while pend:
-        drain(pend.pop(0))
+        for k in range(len(blocks)):
+            compress(k)
+            if k + 1 < len(blocks):
+                stage(k + 1)
+            drain(k)
+        copy_out.synchronize()
+    finally:
+        copier.close()
+        torch.cuda.synchronize()
     tail = src[n - n % S:].tobytes()
+    out = out_t.numpy()
     out[:HEADER] = np.frombuffer(header(n, S, C, W, MIN, policy, N, rec_off, tail), dtype=np.uint8)
     return out[:rec_off]
 
 
-def decompress_host(stream: np.ndarray, block_bytes: int | None = None) -> np.ndarray:
-    """Decompress a host stream block by block; returns the host bytes."""
+def decompress_host(stream, block_bytes: int | None = None,
+                    threads: int | None = None) -> np.ndarray:
+    """Decompress a host stream block by block; returns the bytes as a uint8
+    numpy array over pinned host memory."""
     import torch
-    s = np.ascontiguousarray(stream).view(np.uint8).reshape(-1)
+    s, _ = _host_bytes(stream)
     n, S, total = gpulz.gpulz_peek_header(s[:HEADER].tobytes())
     if total != s.size:
         raise gpulz.GpulzError(gpulz.GPULZ_ERR_CORRUPT, "stream size")
@@ -143,16 +204,67 @@ def decompress_host(stream: np.ndarray, block_bytes: int | None = None) -> np.nd
     r = int(s[40])
     table = s[HEADER:HEADER + 8 * N].view(np.uint32).reshape(N, 2).astype(np.int64)
     rec_start = HEADER + 8 * N + np.concatenate([[0], np.cumsum(table.sum(axis=1))])
+    if int(rec_start[-1]) != s.size:
+        raise gpulz.GpulzError(gpulz.GPULZ_ERR_CORRUPT, "record sizes")
     block_bytes = block_bytes or default_block_bytes()
-    out = np.empty(n, dtype=np.uint8)
-    for off, nb, c0, nc in block_plan(n, S, C, block_bytes):
-        tail = s[48:48 + r].tobytes() if c0 + nc == N else b""
-        nb_block = nb if c0 + nc == N else nc * C * S
-        recs = s[rec_start[c0]:rec_start[c0 + nc]]
-        tot = HEADER + 8 * nc + recs.size
-        sub = np.concatenate([
-            np.frombuffer(header(nb_block, S, C, W, MIN, policy, nc, tot, tail), dtype=np.uint8),
-            s[HEADER + 8 * c0:HEADER + 8 * (c0 + nc)], recs])
-        d = gpulz.decompress(torch.from_numpy(sub).cuda(), nb_block)
-        out[off:off + nb_block] = d.cpu().numpy()
-    return out
+    blocks = block_plan(n, S, C, block_bytes)
+    subs = []
+    for off, nb, c0, nc in blocks:
+        last = c0 + nc == N
+        nb_block = nb if last else nc * C * S
+        tot = HEADER + 8 * nc + int(rec_start[c0 + nc] - rec_start[c0])
+        hdr = header(nb_block, S, C, W, MIN, policy, nc, tot, s[48:48 + r].tobytes() if last else b"")
+        subs.append((off, nb_block, c0, nc, tot, hdr))
+    smax = max(1, max(t for *_, t, _ in subs))
+    bmax = max(1, max(b for _, b, *_ in subs))
+    out_t = torch.empty(max(n, 1), dtype=torch.uint8, pin_memory=True)
+    pin = [torch.empty(smax, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
+    dev_in = [torch.empty(smax, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    dev_out = [torch.empty(bmax, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    ws_bytes = gpulz.gpulz_decompress_workspace_size(smax)
+    ws = [torch.empty(ws_bytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    meta = torch.zeros(len(subs), 2, dtype=torch.int64, device="cuda")
+    copy_in, work, copy_out = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    loaded = [torch.cuda.Event() for _ in range(2)]
+    decoded = [torch.cuda.Event() for _ in range(2)]
+    copied = [torch.cuda.Event() for _ in range(2)]
+    used = [False, False]
+    copier = _Copier(threads or default_threads())
+    try:
+        for k, (off, nb, c0, nc, tot, hdr) in enumerate(subs):
+            j = k % 2
+            if used[j]:
+                loaded[j].synchronize()
+                copy_in.wait_event(decoded[j])
+            p = pin[j].numpy()
+            p[:HEADER] = np.frombuffer(hdr, dtype=np.uint8)
+            p[HEADER:HEADER + 8 * nc] = s[HEADER + 8 * c0:HEADER + 8 * (c0 + nc)]
+            copier(p[HEADER + 8 * nc:tot], s[rec_start[c0]:rec_start[c0 + nc]])
+            with torch.cuda.stream(copy_in):
+                dev_in[j][:tot].copy_(pin[j][:tot], non_blocking=True)
+                loaded[j].record(copy_in)
+            work.wait_event(loaded[j])
+            if used[j]:
+                work.wait_event(copied[j])
+            st = gpulz.gpulz_decompress(dev_in[j].data_ptr(), tot, dev_out[j].data_ptr(), nb,
+                                        meta[k].data_ptr(), meta[k].data_ptr() + 8,
+                                        ws[j].data_ptr(), ws_bytes, gpulz._stream_handle(work))
+            gpulz._check(st, "gpulz_decompress")
+            decoded[j].record(work)
+            with torch.cuda.stream(copy_out):
+                copy_out.wait_event(decoded[j])
+                out_t[off:off + nb].copy_(dev_out[j][:nb], non_blocking=True)
+                copied[j].record(copy_out)
+            used[j] = True
+        copy_out.synchronize()
+    finally:
+        copier.close()
+        torch.cuda.synchronize()
+    m = meta.cpu().numpy()
+    for k, (_, nb, *_rest) in enumerate(subs):
+        status = int(m[k, 1]) & 0xFFFFFFFF
+        if status != gpulz.GPULZ_OK:
+            raise gpulz.GpulzError(status, f"block {k} decompress")
+        if int(m[k, 0]) != nb:
+            raise gpulz.GpulzError(gpulz.GPULZ_ERR_CORRUPT, f"block {k} size")
+    return out_t.numpy()[:n]

@@ -28,3 +28,26 @@ def test_tiny_inputs(n):
     s = stream_host.compress_host(x, 4, 16, 8, 2, block_bytes=64)
     assert s.tobytes() == oracle.compress(x, 4, 16, 8, 2)
     assert stream_host.decompress_host(s, block_bytes=64).tobytes() == x.tobytes()
+
+
+def test_pinned_tensor_input_is_copied_from_directly():
+    import torch
+    x = synth.mixed(600_001, 4, seed=5)
+    t = torch.from_numpy(x.view(np.uint8).copy()).pin_memory()
+    s = stream_host.compress_host(t, 4, 512, 128, 2, block_bytes=40 << 10, threads=4)
+    assert s.tobytes() == oracle.compress(x, 4, 512, 128, 2)
+    d = stream_host.decompress_host(torch.from_numpy(s.copy()), block_bytes=70 << 10, threads=3)
+    assert d.tobytes() == x.tobytes()
+
+
+def test_corrupt_record_in_one_block_is_reported():
+    from paper_2304_07342_amd import gpulz
+    x = synth.mixed(200_000, 4, seed=9)
+    s = bytearray(oracle.compress(x, 4, 256, 64, 2))
+    N = -(-(x.nbytes // 4) // 256)
+    table = np.frombuffer(bytes(s[64:64 + 8 * N]), np.uint32).reshape(N, 2).astype(np.int64)
+    k = 150   # a chunk of a later block (32 chunks per block below)
+    rec = 64 + 8 * N + int(table[:k].sum())
+    s[rec] ^= 0xFF   # its first flag byte: the token kinds no longer fit the payload size
+    with pytest.raises(gpulz.GpulzError):
+        stream_host.decompress_host(np.frombuffer(bytes(s), np.uint8), block_bytes=32 << 10)

@@ -25,3 +25,14 @@ def test_header_layout():
     h = stream_host.header(10, 4, 2, 8, 2, 1, 1, 99, b"\x01\x02")
     assert len(h) == 64 and h[:4] == b"GLZ1" and h[6] == 4 and h[7] == 1 and h[40] == 2
     assert h[48:50] == b"\x01\x02" and h[50:] == bytes(14)
+
+
+def test_record_sizes_must_cover_the_stream():
+    import numpy as np
+    import oracle
+    from paper_2304_07342_amd import gpulz
+    x = np.arange(4096, dtype=np.uint32)
+    s = bytearray(oracle.compress(x.tobytes(), 4, 256, 64, 2))
+    s[64] ^= 1    # first chunk's flag-byte count no longer matches the records
+    with pytest.raises(gpulz.GpulzError):
+        stream_host.decompress_host(np.frombuffer(bytes(s), np.uint8), block_bytes=4096)
