@@ -1,13 +1,15 @@
-"""CPU oracle for chunked multi-byte LZSS (gpuLZ, Zhang et al., ICS'23).
+"""CPU oracle for chunked multi-byte LZSS (gpuLZ, Zhang et al., ICS'23) and
+the Huffman stage that follows it.
 
 TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
 benchmark's CPU-baseline leg may import this package. The product library
 (``paper_2304_07342_amd``) never imports, loads or calls it, and the two
 share no code.
 
-The oracle is plain C99 (``gpulz_oracle.c``) built with gcc into
-``libgpulz_oracle.so`` and loaded here with ctypes. See the C header for what
-it computes and which passage of the paper each step follows.
+The oracle is plain C99 (``gpulz_oracle.c`` for LZSS, ``huff_oracle.c`` for
+the Huffman stage; the two files are independent) built with gcc into
+``libgpulz_oracle.so`` and loaded here with ctypes. See the C headers for
+what each computes and which passage of the paper each step follows.
 """
 from __future__ import annotations
 
@@ -19,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gpulz_oracle.c")
+_HUFF_SRC = os.path.join(_HERE, "huff_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libgpulz_oracle.so")
 
 OK = 0
@@ -34,7 +37,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(
             ["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-shared", "-fPIC",
-             "-pthread", _SRC, "-o", tmp])
+             "-pthread", _SRC, _HUFF_SRC, "-o", tmp])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -74,6 +77,16 @@ def _load():
         lib.oracle_parse_chunk.restype = ctypes.c_int64
         lib.oracle_parse_chunk.argtypes = [u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                            ctypes.c_uint32, u32p, u32p]
+        lib.oracle_huff_lengths.restype = ctypes.c_int
+        lib.oracle_huff_lengths.argtypes = [u64p, ctypes.c_uint32, u8p]
+        lib.oracle_huff_codes.restype = None
+        lib.oracle_huff_codes.argtypes = [u8p, u32p]
+        lib.oracle_huff_bound.restype = ctypes.c_uint64
+        lib.oracle_huff_bound.argtypes = [ctypes.c_uint64]
+        lib.oracle_huff_compress.restype = ctypes.c_int
+        lib.oracle_huff_compress.argtypes = [u8p, ctypes.c_uint64, u8p, ctypes.c_uint64, u64p]
+        lib.oracle_huff_decompress.restype = ctypes.c_int
+        lib.oracle_huff_decompress.argtypes = [u8p, ctypes.c_uint64, u8p, ctypes.c_uint64, u64p]
         _lib = lib
     return _lib
 
@@ -165,3 +178,64 @@ def parse_chunk(chunk, symbol_bytes: int, window: int, min_match: int, policy: i
     if t < 0:
         raise ValueError("invalid parameters")
     return [(int(lengths[i]), int(offsets[i])) for i in range(t)]
+
+
+# ---- Huffman stage ------------------------------------------------------------
+
+def huff_lengths(freq, max_len: int = 15):
+    """Code lengths (list of 256) for byte frequencies; None if max_len
+    cannot hold the present symbols."""
+    f = np.zeros(256, dtype=np.uint64)
+    f[:len(freq)] = np.asarray(freq, dtype=np.uint64)
+    out = np.zeros(256, dtype=np.uint8)
+    st = _load().oracle_huff_lengths(f.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), max_len,
+                                     _u8(out))
+    return None if st else [int(v) for v in out]
+
+
+def huff_codes(lengths):
+    ln = np.zeros(256, dtype=np.uint8)
+    ln[:len(lengths)] = lengths
+    out = np.zeros(256, dtype=np.uint32)
+    _load().oracle_huff_codes(_u8(ln), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    return [int(v) for v in out]
+
+
+def huff_bound(nbytes: int) -> int:
+    return int(_load().oracle_huff_bound(nbytes))
+
+
+def huff_compress(data) -> bytes:
+    lib = _load()
+    x = _as_bytes(data)
+    cap = lib.oracle_huff_bound(x.size)
+    out = np.zeros(cap, dtype=np.uint8)
+    out_len = ctypes.c_uint64(0)
+    xin = x if x.size else np.zeros(1, dtype=np.uint8)
+    st = lib.oracle_huff_compress(_u8(xin), x.size, _u8(out), cap, ctypes.byref(out_len))
+    if st != OK:
+        raise ValueError(f"oracle_huff_compress failed with status {st}")
+    return out[: out_len.value].tobytes()
+
+
+def huff_decompress_status(stream, capacity: int | None = None):
+    """Return (status, original_bytes_or_None, n)."""
+    lib = _load()
+    s = _as_bytes(stream)
+    if capacity is None:
+        capacity = int.from_bytes(bytes(s[16:24]), "little") if s.size >= 64 else 0
+        capacity = min(capacity, 1 << 34)
+    out = np.zeros(max(capacity, 1), dtype=np.uint8)
+    out_len = ctypes.c_uint64(0)
+    sin = s if s.size else np.zeros(1, dtype=np.uint8)
+    st = lib.oracle_huff_decompress(_u8(sin), s.size, _u8(out), capacity, ctypes.byref(out_len))
+    if st == OK:
+        return st, out[: out_len.value].tobytes(), out_len.value
+    return st, None, out_len.value
+
+
+def huff_decompress(stream) -> bytes:
+    st, data, _ = huff_decompress_status(stream)
+    if st != OK:
+        raise ValueError(f"oracle_huff_decompress failed with status {st}")
+    return data
