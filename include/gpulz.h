@@ -221,12 +221,77 @@ gpulz_status gpulz_decompress_batch(uint64_t nbufs, const void* const* d_in_ptrs
                                     int32_t* d_status, uint64_t max_total_in_bytes,
                                     void* d_workspace, size_t ws_bytes, hipStream_t stream);
 
+/* ---- Entropy stage: Huffman coding of bytes ---------------------------------
+ *
+ * gpuLZ (section 4.5) places the LZSS stage in front of a Huffman coder; these
+ * calls provide that coder for any byte buffer (an LZSS stream, or raw
+ * bytes). The paper does not specify the coder, so the code is defined as:
+ *   - one code for the input, from its byte frequencies, by Huffman's
+ *     algorithm: repeatedly join the two nodes of smallest (weight, index),
+ *     where leaves are indexed 0-255 by symbol and internal nodes 256, 257,
+ *     ... in the order they are made; a symbol's length is its depth. One
+ *     distinct symbol gets length 1. If a length exceeds 15, every weight w
+ *     becomes ceil(w / 2) and the tree is built again;
+ *   - canonical codes (RFC 1951 section 3.2.2).
+ * Stream layout (little-endian):
+ *   0..3 "GLH1"; 4..5 version 1; 6 15 (longest code); 7 0;
+ *   8..11 4096 (chunk bytes); 12..15 128 (sub-block bytes);
+ *   16..23 n; 24..31 N = ceil(n / 4096); 32..39 total stream bytes;
+ *   40..63 zero;
+ *   64..191 code lengths, symbol 2k in bits 0-3 and 2k + 1 in bits 4-7 of
+ *           byte 64 + k;
+ *   192..  N u32 bits_i (code bits of chunk i);
+ *   then per chunk: ceil(c_i / 128) u16 start bits of its 128-byte
+ *   sub-blocks (the first is 0), zero-padded to a multiple of 4 bytes, then
+ *   ceil(bits_i / 32) u32 words, bit k of the chunk = bit 31 - (k % 32) of
+ *   word k / 32, unused bits zero (c_i = min(4096, n - 4096 i)). */
+
+/* Largest stream for an input of n bytes (0 if n exceeds 2^40). Host-only. */
+uint64_t gpulz_huff_compress_bound(uint64_t nbytes);
+
+/* Workspace bytes for gpulz_huff_compress with inputs of up to max_bytes.
+ * Host-only. */
+gpulz_status gpulz_huff_compress_workspace_size(uint64_t max_bytes, size_t* ws_bytes);
+
+/* Huffman-code d_in into d_out. The input size is `nbytes`, or, when
+ * d_nbytes is not NULL, the device value *d_nbytes read by the kernels
+ * (then `nbytes` is its maximum; a larger value gives *d_status =
+ * GPULZ_ERR_INVALID_ARG and *d_out_bytes = 0). This lets the call follow
+ * gpulz_compress on the same stream with d_nbytes = that call's d_out_bytes,
+ * with no host round trip. out_capacity must be at least
+ * gpulz_huff_compress_bound(nbytes) (else GPULZ_ERR_OUT_OF_SPACE, nothing
+ * launched). d_in and d_out 16-byte aligned, d_workspace 256-byte aligned
+ * (else GPULZ_ERR_INVALID_ARG); workspace as sized above (else
+ * GPULZ_ERR_WORKSPACE). Writes *d_out_bytes and *d_status = GPULZ_OK.
+ * Asynchronous on `stream`; the caller owns every buffer. */
+gpulz_status gpulz_huff_compress(const void* d_in, uint64_t nbytes, const uint64_t* d_nbytes,
+                                 void* d_out, uint64_t out_capacity, uint64_t* d_out_bytes,
+                                 int32_t* d_status, void* d_workspace, size_t ws_bytes,
+                                 hipStream_t stream);
+
+/* Workspace bytes for gpulz_huff_decompress of a stream of stream_bytes.
+ * Host-only. */
+gpulz_status gpulz_huff_decompress_workspace_size(uint64_t stream_bytes, size_t* ws_bytes);
+
+/* Decode a Huffman stream d_in[0..in_bytes) into d_out. Every rule of the
+ * layout is checked: header fields, a code that is complete (or one symbol
+ * of length 1, or no symbol for n = 0), record sizes that tile the stream,
+ * each sub-block decoding exactly its symbols from its start bit to the next
+ * one's, zero padding. Writes *d_status = GPULZ_OK, GPULZ_ERR_CORRUPT (d_out
+ * contents unspecified) or GPULZ_ERR_OUT_OF_SPACE (out_capacity < n; nothing
+ * written), and *d_out_bytes = n (0 for a bad header). Alignment and
+ * workspace rules as gpulz_huff_compress. Asynchronous on `stream`. */
+gpulz_status gpulz_huff_decompress(const void* d_in, uint64_t in_bytes, void* d_out,
+                                   uint64_t out_capacity, uint64_t* d_out_bytes, int32_t* d_status,
+                                   void* d_workspace, size_t ws_bytes, hipStream_t stream);
+
 /* Kernel timing for benchmarks. While enabled, every gpulz_compress and
  * gpulz_decompress call records a pair of HIP events on its own stream
  * around each kernel it launches, so the times cover exactly those kernels.
  * Kernel ids: 0 chunk encode, 1 global scan + header, 2 record scatter,
  * 3 decode prepare (header check + table scan), 4 chunk decode, 5 a whole
- * gpulz_compress_batch call, 6 a whole gpulz_decompress_batch call.
+ * gpulz_compress_batch call, 6 a whole gpulz_decompress_batch call, 7 a
+ * whole gpulz_huff_compress call, 8 a whole gpulz_huff_decompress call.
  * gpulz_profile_enable(1) clears the accumulated times, (0) stops recording.
  * gpulz_profile_read waits for the recorded events and writes, for each of
  * the first `nkernels` ids, the summed milliseconds and the launch count

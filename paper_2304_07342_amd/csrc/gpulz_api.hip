@@ -7,13 +7,14 @@
 #include <vector>
 
 #include "gpulz_internal.h"
+#include "huff_internal.h"
 
 using namespace gpulz;
 
 namespace {
 
 // ---- optional per-kernel event timing ---------------------------------------
-constexpr int kProfKernels = 7;
+constexpr int kProfKernels = 9;
 struct EventPair {
   int kernel;
   hipEvent_t start, stop;
@@ -423,6 +424,78 @@ gpulz_status gpulz_profile_enable(int enable) {
   }
   g_prof_events.clear();
   g_prof_on = enable != 0;
+  return GPULZ_OK;
+}
+
+// ---- entropy stage ------------------------------------------------------------
+
+uint64_t gpulz_huff_compress_bound(uint64_t nbytes) {
+  return nbytes > huff::kMaxInput ? 0 : huff::bound(nbytes);
+}
+
+gpulz_status gpulz_huff_compress_workspace_size(uint64_t max_bytes, size_t* ws_bytes) {
+  if (!ws_bytes || max_bytes > huff::kMaxInput) return GPULZ_ERR_INVALID_ARG;
+  *ws_bytes = (size_t)huff::enc_workspace(max_bytes).total;
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_huff_compress(const void* d_in, uint64_t nbytes, const uint64_t* d_nbytes,
+                                 void* d_out, uint64_t out_capacity, uint64_t* d_out_bytes,
+                                 int32_t* d_status, void* d_ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+  if ((nbytes && !d_in) || !d_out || !d_out_bytes || !d_status || nbytes > huff::kMaxInput)
+    return GPULZ_ERR_INVALID_ARG;
+  if (!aligned(d_in, 16) || !aligned(d_out, 16) || !aligned(d_ws, 256)) return GPULZ_ERR_INVALID_ARG;
+  if (out_capacity < huff::bound(nbytes)) return GPULZ_ERR_OUT_OF_SPACE;
+  const huff::EncWorkspace w = huff::enc_workspace(nbytes);
+  if (!d_ws || ws_bytes < w.total) return GPULZ_ERR_WORKSPACE;
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  huff::EncArgs a;
+  a.in = static_cast<const uint8_t*>(d_in);
+  a.max_n = nbytes;
+  a.d_n = d_nbytes;
+  a.hist_blocks = huff::hist_blocks(nbytes);
+  a.partial = reinterpret_cast<uint32_t*>(ws + w.partial_off);
+  a.codes = reinterpret_cast<uint32_t*>(ws + w.codes_off);
+  a.sizes = reinterpret_cast<uint32_t*>(ws + w.sizes_off);
+  a.offs = reinterpret_cast<uint64_t*>(ws + w.offs_off);
+  a.out = static_cast<uint8_t*>(d_out);
+  a.out_bytes = d_out_bytes;
+  a.status = d_status;
+  const int pi = prof_begin(7, stream);
+  if (huff::launch_compress(a, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  prof_end(pi, stream);
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_huff_decompress_workspace_size(uint64_t stream_bytes, size_t* ws_bytes) {
+  if (!ws_bytes) return GPULZ_ERR_INVALID_ARG;
+  *ws_bytes = (size_t)huff::dec_workspace(stream_bytes).total;
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_huff_decompress(const void* d_in, uint64_t in_bytes, void* d_out,
+                                   uint64_t out_capacity, uint64_t* d_out_bytes, int32_t* d_status,
+                                   void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  if ((in_bytes && !d_in) || !d_out_bytes || !d_status || (out_capacity && !d_out))
+    return GPULZ_ERR_INVALID_ARG;
+  if (!aligned(d_in, 16) || !aligned(d_out, 16) || !aligned(d_ws, 256)) return GPULZ_ERR_INVALID_ARG;
+  const huff::DecWorkspace w = huff::dec_workspace(in_bytes);
+  if (!d_ws || ws_bytes < w.total) return GPULZ_ERR_WORKSPACE;
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  huff::DecArgs a;
+  a.in = static_cast<const uint8_t*>(d_in);
+  a.in_bytes = in_bytes;
+  a.capacity = out_capacity;
+  a.tab = reinterpret_cast<huff::DecTables*>(ws);
+  a.sizes = reinterpret_cast<uint32_t*>(ws + w.sizes_off);
+  a.offs = reinterpret_cast<uint64_t*>(ws + w.offs_off);
+  a.out = static_cast<uint8_t*>(d_out);
+  a.out_bytes = d_out_bytes;
+  a.status = d_status;
+  const int pi = prof_begin(8, stream);
+  if (huff::launch_decompress(a, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  prof_end(pi, stream);
   return GPULZ_OK;
 }
 

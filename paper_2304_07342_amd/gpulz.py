@@ -29,10 +29,11 @@ EXPORTS = (
     "gpulz_decompress_workspace_size", "gpulz_decompress", "gpulz_default_params",
     "gpulz_set_default_params", "gpulz_compress_batch_workspace_size", "gpulz_compress_batch",
     "gpulz_decompress_batch_workspace_size", "gpulz_decompress_batch", "gpulz_profile_enable",
-    "gpulz_profile_read",
+    "gpulz_profile_read", "gpulz_huff_compress_bound", "gpulz_huff_compress_workspace_size",
+    "gpulz_huff_compress", "gpulz_huff_decompress_workspace_size", "gpulz_huff_decompress",
 )
 KERNEL_NAMES = ("encode", "scan", "scatter", "decode_prepare", "decode", "compress_batch",
-                "decompress_batch")
+                "decompress_batch", "huff_compress", "huff_decompress")
 
 
 class Params(ctypes.Structure):
@@ -111,6 +112,16 @@ def lib() -> ctypes.CDLL:
         L.gpulz_profile_read.restype = ctypes.c_int
         L.gpulz_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
                                          ctypes.c_int]
+        L.gpulz_huff_compress_bound.restype = u64
+        L.gpulz_huff_compress_bound.argtypes = [u64]
+        L.gpulz_huff_compress_workspace_size.restype = ctypes.c_int
+        L.gpulz_huff_compress_workspace_size.argtypes = [u64, ctypes.POINTER(sz)]
+        L.gpulz_huff_compress.restype = ctypes.c_int
+        L.gpulz_huff_compress.argtypes = [vp, u64, vp, vp, u64, vp, vp, vp, sz, vp]
+        L.gpulz_huff_decompress_workspace_size.restype = ctypes.c_int
+        L.gpulz_huff_decompress_workspace_size.argtypes = [u64, ctypes.POINTER(sz)]
+        L.gpulz_huff_decompress.restype = ctypes.c_int
+        L.gpulz_huff_decompress.argtypes = [vp, u64, vp, u64, vp, vp, vp, sz, vp]
         _lib = L
     return _lib
 
@@ -177,6 +188,40 @@ def gpulz_decompress(d_in: int, in_bytes: int, d_out: int, out_capacity: int, d_
                      d_status: int, d_workspace: int, ws_bytes: int, stream: int = 0) -> int:
     return lib().gpulz_decompress(d_in, in_bytes, d_out, out_capacity, d_out_bytes, d_status,
                                   d_workspace, ws_bytes, stream)
+
+
+def gpulz_huff_compress_bound(nbytes: int) -> int:
+    return int(lib().gpulz_huff_compress_bound(nbytes))
+
+
+def gpulz_huff_compress_workspace_size(max_bytes: int) -> int:
+    ws = ctypes.c_size_t(0)
+    st = lib().gpulz_huff_compress_workspace_size(max_bytes, ctypes.byref(ws))
+    if st != GPULZ_OK:
+        raise GpulzError(st, "gpulz_huff_compress_workspace_size")
+    return ws.value
+
+
+def gpulz_huff_compress(d_in: int, nbytes: int, d_nbytes, d_out: int, out_capacity: int,
+                        d_out_bytes: int, d_status: int, d_workspace: int, ws_bytes: int,
+                        stream: int = 0) -> int:
+    return lib().gpulz_huff_compress(d_in, nbytes, d_nbytes, d_out, out_capacity, d_out_bytes,
+                                     d_status, d_workspace, ws_bytes, stream)
+
+
+def gpulz_huff_decompress_workspace_size(stream_bytes: int) -> int:
+    ws = ctypes.c_size_t(0)
+    st = lib().gpulz_huff_decompress_workspace_size(stream_bytes, ctypes.byref(ws))
+    if st != GPULZ_OK:
+        raise GpulzError(st, "gpulz_huff_decompress_workspace_size")
+    return ws.value
+
+
+def gpulz_huff_decompress(d_in: int, in_bytes: int, d_out: int, out_capacity: int,
+                          d_out_bytes: int, d_status: int, d_workspace: int, ws_bytes: int,
+                          stream: int = 0) -> int:
+    return lib().gpulz_huff_decompress(d_in, in_bytes, d_out, out_capacity, d_out_bytes, d_status,
+                                       d_workspace, ws_bytes, stream)
 
 
 def gpulz_default_params(symbol_bytes: int):
@@ -323,6 +368,105 @@ def decompress(s, out_capacity: int | None = None, stream=None, return_status: b
         return status, out[:n] if status == GPULZ_OK else None
     _check(status, "gpulz_decompress (device status)")
     return out[:n]
+
+
+# ---- entropy stage (Huffman) -----------------------------------------------------
+
+class HuffCompressor:
+    """Reusable device buffers for Huffman-coding inputs of up to
+    `max_bytes`. `compress_async` only enqueues kernels; `result` reads back
+    the size and status (synchronising)."""
+
+    def __init__(self, max_bytes: int, device="cuda"):
+        torch = _torch()
+        self.max_bytes = max_bytes
+        self.capacity = gpulz_huff_compress_bound(max_bytes)
+        if self.capacity == 0:
+            raise GpulzError(GPULZ_ERR_INVALID_ARG, "gpulz_huff_compress_bound")
+        self.ws_bytes = gpulz_huff_compress_workspace_size(max_bytes)
+        self.out = torch.empty(self.capacity, dtype=torch.uint8, device=device)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.meta = torch.zeros(2, dtype=torch.int64, device=device)  # [out_bytes, status]
+
+    def compress_async(self, x, nbytes: int | None = None, d_nbytes: int | None = None,
+                       stream=None) -> None:
+        """`x` is a device tensor (or an integer device pointer with `nbytes`);
+        `d_nbytes` is an optional device pointer to the actual size (u64),
+        read by the kernels, with `nbytes` its maximum."""
+        ptr = x if isinstance(x, int) else x.data_ptr()
+        if nbytes is None:
+            nbytes = x.numel() * x.element_size()
+        st = gpulz_huff_compress(ptr, nbytes, d_nbytes, self.out.data_ptr(), self.capacity,
+                                 self.meta.data_ptr(), self.meta.data_ptr() + 8, self.ws.data_ptr(),
+                                 self.ws_bytes, _stream_handle(stream))
+        _check(st, "gpulz_huff_compress")
+
+    def result(self):
+        meta = self.meta.cpu()
+        return int(meta[0]), int(meta[1]) & 0xFFFFFFFF
+
+
+def huff_compress(x, stream=None):
+    """Huffman-code a device tensor's bytes; returns a uint8 device tensor."""
+    nbytes = x.numel() * x.element_size()
+    c = HuffCompressor(max(nbytes, 1), device=x.device)
+    c.compress_async(x, nbytes, stream=stream)
+    size, status = c.result()
+    _check(status, "gpulz_huff_compress (device status)")
+    return c.out[:size]
+
+
+def huff_stream_size(s) -> int:
+    """n, the decoded size, from a Huffman stream's header (device tensor)."""
+    if s.numel() < 64:
+        return 0
+    h = bytes(s[:64].cpu().numpy())
+    return int.from_bytes(h[16:24], "little") if h[:4] == b"GLH1" else 0
+
+
+def huff_decompress(s, out_capacity: int | None = None, stream=None, return_status: bool = False):
+    """Decode a Huffman stream held in a uint8 device tensor."""
+    torch = _torch()
+    in_bytes = s.numel()
+    if out_capacity is None:
+        out_capacity = huff_stream_size(s)
+    ws_bytes = gpulz_huff_decompress_workspace_size(in_bytes)
+    out = torch.empty(max(out_capacity, 1), dtype=torch.uint8, device=s.device)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=s.device)
+    meta = torch.zeros(2, dtype=torch.int64, device=s.device)
+    st = gpulz_huff_decompress(s.data_ptr(), in_bytes, out.data_ptr(), out_capacity,
+                               meta.data_ptr(), meta.data_ptr() + 8, ws.data_ptr(), ws_bytes,
+                               _stream_handle(stream))
+    _check(st, "gpulz_huff_decompress")
+    m = meta.cpu()
+    n, status = int(m[0]), int(m[1]) & 0xFFFFFFFF
+    if return_status:
+        return status, out[:n] if status == GPULZ_OK else None
+    _check(status, "gpulz_huff_decompress (device status)")
+    return out[:n]
+
+
+def compress_entropy(x, symbol_bytes: int, chunk_symbols: int, window: int, min_match: int,
+                     stream=None, policy: int = 0):
+    """LZSS, then Huffman coding of the LZSS stream, enqueued back to back on
+    one stream (the Huffman stage reads the LZSS size on the device).
+    Returns (Huffman stream, LZSS stream bytes) as (device tensor, int)."""
+    nbytes = x.numel() * x.element_size()
+    lz = Compressor(max(nbytes, 1), symbol_bytes, chunk_symbols, window, min_match,
+                    device=x.device, policy=policy)
+    hc = HuffCompressor(lz.capacity, device=x.device)
+    lz.compress_async(x, nbytes, stream)
+    hc.compress_async(lz.out.data_ptr(), lz.capacity, d_nbytes=lz.meta.data_ptr(), stream=stream)
+    lz_size, lz_status = lz.result()
+    _check(lz_status, "gpulz_compress (device status)")
+    size, status = hc.result()
+    _check(status, "gpulz_huff_compress (device status)")
+    return hc.out[:size], lz_size
+
+
+def decompress_entropy(s, stream=None):
+    """Inverse of compress_entropy: Huffman decoding, then LZSS decoding."""
+    return decompress(huff_decompress(s, stream=stream), stream=stream)
 
 
 # ---- batches ------------------------------------------------------------------

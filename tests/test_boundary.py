@@ -172,3 +172,40 @@ def test_batch_rejects_bad_host_arguments():
         == gpulz.GPULZ_ERR_WORKSPACE
     assert gpulz.gpulz_decompress_batch(4, None, FAKE, FAKE, FAKE, FAKE, FAKE, 4096, FAKE, dws) \
         == gpulz.GPULZ_ERR_INVALID_ARG
+
+
+# ---- entropy stage ----------------------------------------------------------
+
+@pytest.mark.parametrize("n", [0, 1, 4095, 4096, 4097, 1 << 20, 10**9])
+def test_huff_bound_matches_oracle(n):
+    assert gpulz.gpulz_huff_compress_bound(n) == oracle.huff_bound(n)
+
+
+def test_huff_bound_and_workspace_limits():
+    assert gpulz.gpulz_huff_compress_bound((1 << 40) + 1) == 0
+    with pytest.raises(gpulz.GpulzError):
+        gpulz.gpulz_huff_compress_workspace_size((1 << 40) + 1)
+    a = gpulz.gpulz_huff_compress_workspace_size(1 << 20)
+    b = gpulz.gpulz_huff_compress_workspace_size(1 << 24)
+    assert 0 < a < b
+    assert 0 < gpulz.gpulz_huff_decompress_workspace_size(1 << 20) < \
+        gpulz.gpulz_huff_decompress_workspace_size(1 << 24)
+
+
+def test_huff_host_argument_errors():
+    n = 1 << 16
+    cap = gpulz.gpulz_huff_compress_bound(n)
+    ws = gpulz.gpulz_huff_compress_workspace_size(n)
+    c = gpulz.gpulz_huff_compress
+    assert c(FAKE + 1, n, None, FAKE, cap, FAKE, FAKE, FAKE, ws) == gpulz.GPULZ_ERR_INVALID_ARG
+    assert c(FAKE, n, None, FAKE + 8, cap, FAKE, FAKE, FAKE, ws) == gpulz.GPULZ_ERR_INVALID_ARG
+    assert c(FAKE, n, None, FAKE, cap, FAKE, FAKE, FAKE + 16, ws) == gpulz.GPULZ_ERR_INVALID_ARG
+    assert c(FAKE, n, None, FAKE, cap - 1, FAKE, FAKE, FAKE, ws) == gpulz.GPULZ_ERR_OUT_OF_SPACE
+    assert c(FAKE, n, None, FAKE, cap, FAKE, FAKE, FAKE, ws - 1) == gpulz.GPULZ_ERR_WORKSPACE
+    assert c(FAKE, (1 << 40) + 1, None, FAKE, cap, FAKE, FAKE, FAKE, ws) == \
+        gpulz.GPULZ_ERR_INVALID_ARG
+    d = gpulz.gpulz_huff_decompress
+    wsd = gpulz.gpulz_huff_decompress_workspace_size(n)
+    assert d(FAKE + 4, n, FAKE, n, FAKE, FAKE, FAKE, wsd) == gpulz.GPULZ_ERR_INVALID_ARG
+    assert d(FAKE, n, FAKE, n, FAKE, FAKE, FAKE, wsd - 1) == gpulz.GPULZ_ERR_WORKSPACE
+    assert d(FAKE, n, FAKE, n, 0, FAKE, FAKE, wsd) == gpulz.GPULZ_ERR_INVALID_ARG
