@@ -18,6 +18,8 @@ Other workloads (--workload), each printing its own JSON lines:
           content kind, against the element-width default;
   host    a 1 GiB host-resident input streamed through the GPU in blocks
           (PCIe included);
+  entropy 256 MiB of uint16 codes through LZSS then the Huffman stage, and
+          back;
   sweep   1 GiB per symbol width (Zipf bytes, Laplace uint16 codes, sorted
           uint32 indices, float64 field), parameters from the autotuner;
   batch   4096 buffers, log-uniform 4 KiB..64 MiB, mixed widths, one
@@ -366,6 +368,100 @@ def run_host(args):
                       "runs": runs}), flush=True)
 
 
+def run_entropy(args):
+    """The entropy stage after LZSS (section 4.5 pairs gpuLZ with a Huffman
+    coder): 256 MiB of uint16 quantization codes (the cuSZ stand-in) through
+    LZSS (S=2, C=2048, W=128, MIN=2), Huffman on the LZSS stream, the two
+    chained on one stream, Huffman on the raw codes, and the decoders; GB/s
+    of each (over its own input bytes) and ratios."""
+    import torch
+    from paper_2304_07342_amd import gpulz, synth
+    x = torch.from_numpy(synth.laplace_codes_pool(1 << 27, seed=7).view(np.uint8)).to("cuda")
+    n = x.numel()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    def huff_decoder(s, cap):
+        out = torch.empty(max(cap, 1), dtype=torch.uint8, device="cuda")
+        ws_bytes = gpulz.gpulz_huff_decompress_workspace_size(s.numel())
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        meta = torch.zeros(2, dtype=torch.int64, device="cuda")
+
+        def run():
+            gpulz._check(gpulz.gpulz_huff_decompress(
+                s.data_ptr(), s.numel(), out.data_ptr(), cap, meta.data_ptr(),
+                meta.data_ptr() + 8, ws.data_ptr(), ws_bytes, stream.cuda_stream), "huff decode")
+        return run, out, meta
+
+    lz = gpulz.Compressor(n, 2, 2048, 128, 2)
+    lz_ms = timed(lambda: lz.compress_async(x))
+    lz_size, st = lz.result()
+    assert st == gpulz.GPULZ_OK
+    lz_stream = lz.out[:lz_size].clone()
+    hc = gpulz.HuffCompressor(lz.capacity)
+    huff_ms = timed(lambda: hc.compress_async(lz_stream))
+    h_size, st = hc.result()
+    assert st == gpulz.GPULZ_OK
+
+    def chain():
+        lz.compress_async(x)
+        hc.compress_async(lz.out.data_ptr(), lz.capacity, d_nbytes=lz.meta.data_ptr())
+    chain_ms = timed(chain)
+    c_size, st = hc.result()
+    assert st == gpulz.GPULZ_OK and c_size == h_size
+    chain_stream = hc.out[:c_size].clone()
+    raw = gpulz.HuffCompressor(n)
+    raw_ms = timed(lambda: raw.compress_async(x))
+    raw_size, st = raw.result()
+    assert st == gpulz.GPULZ_OK
+
+    hdec, hout, hmeta = huff_decoder(chain_stream, lz_size)
+    hdec_ms = timed(hdec)
+    if int(hmeta[1]) != 0 or not torch.equal(hout[:lz_size], lz_stream):
+        raise SystemExit("Huffman decode mismatch")
+    lz_out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    lz_ws_bytes = gpulz.gpulz_decompress_workspace_size(lz_size)
+    lz_ws = torch.empty(lz_ws_bytes, dtype=torch.uint8, device="cuda")
+    lz_meta = torch.zeros(2, dtype=torch.int64, device="cuda")
+
+    def lz_dec():
+        gpulz._check(gpulz.gpulz_decompress(hout.data_ptr(), lz_size, lz_out.data_ptr(), n,
+                                            lz_meta.data_ptr(), lz_meta.data_ptr() + 8,
+                                            lz_ws.data_ptr(), lz_ws_bytes, stream.cuda_stream),
+                     "lz decode")
+    lzdec_ms = timed(lz_dec)
+
+    def chain_dec():
+        hdec()
+        lz_dec()
+    chain_dec_ms = timed(chain_dec)
+    if not torch.equal(lz_out, x):
+        raise SystemExit("chain round trip mismatch")
+    print(json.dumps({
+        "metric": "compress GB/s (input) + ratio", "workload": "codes-u16-256MiB-lz-huffman",
+        "input_bytes": n, "lz_bytes": lz_size, "chain_bytes": c_size, "raw_huffman_bytes": raw_size,
+        "steps": args.steps,
+        "lz_ratio": round(n / lz_size, 4), "chain_ratio": round(n / c_size, 4),
+        "raw_huffman_ratio": round(n / raw_size, 4),
+        "lz_GBps": round(n / lz_ms / 1e6, 3),
+        "huffman_on_lz_GBps": round(lz_size / huff_ms / 1e6, 3), "huffman_on_lz_ms": round(huff_ms, 4),
+        "chain_GBps": round(n / chain_ms / 1e6, 3), "chain_ms": round(chain_ms, 4),
+        "huffman_on_codes_GBps": round(n / raw_ms / 1e6, 3),
+        "huffman_decode_GBps": round(lz_size / hdec_ms / 1e6, 3), "huffman_decode_ms": round(hdec_ms, 4),
+        "lz_decode_GBps": round(n / lzdec_ms / 1e6, 3),
+        "chain_decode_GBps": round(n / chain_dec_ms / 1e6, 3)}), flush=True)
+
+
 def run_batch(args):
     import torch
     from paper_2304_07342_amd import gpulz, synth
@@ -440,8 +536,8 @@ def run_batch(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="field",
-                    choices=["field", "small", "scan", "sweep", "adaptive", "host", "batch",
-                             "serve"])
+                    choices=["field", "small", "scan", "sweep", "adaptive", "host", "entropy",
+                             "batch", "serve"])
     ap.add_argument("--sweep-bytes", type=int, default=1 << 30)
     ap.add_argument("--nbufs", type=int, default=4096)
     ap.add_argument("--pool-mib", type=int, default=256)
@@ -475,6 +571,8 @@ def main():
         return run_adaptive(args)
     if args.workload == "host":
         return run_host(args)
+    if args.workload == "entropy":
+        return run_entropy(args)
     if args.workload == "sweep":
         return run_sweep(args)
     if args.workload == "batch":

@@ -3,22 +3,23 @@
 // the code and of the stream are in huff_internal.h and gpulz.h.
 //
 // Compression, five launches on one stream, no host round trip:
-//   hist_kernel    per-workgroup byte histograms (one LDS sub-histogram per
-//                  wave, 16-byte loads);
+//   hist_kernel    per-workgroup byte histograms (32 bank-padded LDS
+//                  sub-histograms, 16-byte loads);
 //   build_kernel   one workgroup: sums the histograms, sorts (weight,
 //                  symbol) keys, runs Huffman's merge with two queues (sorted
 //                  leaves, internal nodes in creation order), limits the
 //                  lengths, assigns canonical codes, writes the code lengths;
 //   size_kernel    one wave per chunk: code bits of the chunk;
 //   scan_kernel    one workgroup: record offsets and the header;
-//   encode_kernel  one workgroup per chunk: bit offsets by a block scan,
-//                  codes ORed into LDS words, the record written once.
+//   encode_kernel  one wave per chunk: bit offsets by a wave scan, codes
+//                  ORed into LDS words, the record written once.
 // Decompression:
 //   dec_prepare_kernel  one workgroup: checks the header and the code,
 //                       builds the lookup tables, scans the record sizes;
 //   decode_kernel       one lane per 128-symbol sub-block (32 lanes per
-//                       chunk), an 11-bit lookup table in LDS, symbols staged
-//                       in LDS and written out in 4-byte stores.
+//                       chunk): code words staged in LDS, a two-level
+//                       lookup table in LDS, symbols staged in LDS and
+//                       written out in consecutive 4-byte stores.
 #include "huff_internal.h"
 #include "stream_device.h"
 #include "wave.h"
@@ -36,11 +37,19 @@ __device__ inline uint32_t byte_of(const uint4& q, uint32_t b) {
 
 // ---- compression -----------------------------------------------------------
 
+// 32 sub-histograms per workgroup, one per lane of a half-wave (lanes l and
+// l + 32 share one), each padded by a word so that the copies of one byte
+// value fall in different LDS banks: a skewed input (most bytes equal) then
+// costs two-way same-address atomics instead of 64-way ones.
+constexpr uint32_t kHistCopies = 32;
+constexpr uint32_t kHistStride = 257;
+
 __global__ __launch_bounds__(256) void hist_kernel(EncArgs a) {
-  __shared__ uint32_t h[4][256];
-  const uint32_t tid = threadIdx.x, wid = tid >> 6;
-  for (uint32_t k = tid; k < 4 * 256; k += 256) (&h[0][0])[k] = 0;
+  __shared__ uint32_t h[kHistCopies * kHistStride];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t k = tid; k < kHistCopies * kHistStride; k += 256) h[k] = 0;
   __syncthreads();
+  uint32_t* mine = h + (tid & (kHistCopies - 1)) * kHistStride;
   const uint64_t n = input_size(a);
   if (n <= a.max_n) {
     const uint64_t words = (n + 15) / 16;
@@ -52,107 +61,181 @@ __global__ __launch_bounds__(256) void hist_kernel(EncArgs a) {
       if (16 * w + 16 <= n) {
         const uint4 q = in4[w];
 #pragma unroll
-        for (uint32_t b = 0; b < 16; ++b) atomicAdd(&h[wid][byte_of(q, b)], 1u);
+        for (uint32_t b = 0; b < 16; ++b) atomicAdd(&mine[byte_of(q, b)], 1u);
       } else {
-        for (uint64_t b = 16 * w; b < n; ++b) atomicAdd(&h[wid][a.in[b]], 1u);
+        for (uint64_t b = 16 * w; b < n; ++b) atomicAdd(&mine[a.in[b]], 1u);
       }
     }
   }
   __syncthreads();
-  a.partial[(uint64_t)blockIdx.x * 256 + tid] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
+  uint32_t sum = 0;
+#pragma unroll 8
+  for (uint32_t c = 0; c < kHistCopies; ++c) sum += h[c * kHistStride + tid];
+  a.partial[(uint64_t)blockIdx.x * 256 + tid] = sum;
 }
 
 struct BuildLds {
-  uint64_t part[4][256];
   uint64_t w[256];    // weight by symbol (0 = absent)
-  uint64_t key[256];  // weight << 8 | symbol, sorted; absent = all ones
+  uint64_t tmp[256];  // unsorted keys
+  uint64_t key[256];  // weight << 8 | symbol, ascending; absent symbols last
   uint64_t iw[256];   // internal node weights in creation order
   uint16_t parent[512];
-  uint8_t depth[256];  // internal node depths
+  uint16_t anc[256], dist[256];  // pointer jumping over internal nodes
   uint8_t len[256];
   uint32_t count[16], next[16];
-  uint32_t present, deepest;
+  uint64_t total;       // sum of the weights
+  uint32_t present, deepest, internal;
 };
+
+// Huffman's merge with two queues: sorted leaves, and internal nodes in
+// creation order (their weights never decrease). A leaf wins a tie (its index
+// is smaller). The four front candidates are read together, so each join
+// costs one LDS round trip. W is uint32_t when the weights sum below 2^31
+// (cheaper compares; used below 2^31 so that no weight equals the 32-bit
+// infinity), else uint64_t. Returns the number of internal nodes.
+template <typename W>
+__device__ uint32_t merge(BuildLds& sm, uint32_t m) {
+  const W kInf = (W)~0ull;
+  uint32_t li = 0, kf = 0, kc = 0;
+  for (uint32_t s = 0; s + 1 < m; ++s) {
+    const W l0 = li < m ? (W)(sm.key[li] >> 8) : kInf;
+    const W l1 = li + 1 < m ? (W)(sm.key[li + 1] >> 8) : kInf;
+    const W i0 = kf < kc ? (W)sm.iw[kf] : kInf;
+    const W i1 = kf + 1 < kc ? (W)sm.iw[kf + 1] : kInf;
+    uint32_t na, nb;
+    W wa, wb;
+    if (l0 <= i0) {
+      na = li;
+      wa = l0;
+      if (l1 <= i0) {
+        nb = li + 1;
+        wb = l1;
+        li += 2;
+      } else {
+        nb = 256 + kf;
+        wb = i0;
+        li += 1;
+        kf += 1;
+      }
+    } else {
+      na = 256 + kf;
+      wa = i0;
+      if (l0 <= i1) {
+        nb = li;
+        wb = l0;
+        li += 1;
+        kf += 1;
+      } else {
+        nb = 256 + kf + 1;
+        wb = i1;
+        kf += 2;
+      }
+    }
+    sm.iw[kc] = (uint64_t)wa + wb;
+    sm.parent[na] = (uint16_t)(256 + kc);
+    sm.parent[nb] = (uint16_t)(256 + kc);
+    ++kc;
+  }
+  return kc;
+}
 
 __global__ __launch_bounds__(1024) void build_kernel(EncArgs a) {
   __shared__ BuildLds sm;
   const uint32_t tid = threadIdx.x;
   if (input_size(a) > a.max_n) return;
-  {
-    const uint32_t col = tid & 255u, q = tid >> 8;
-    uint64_t f = 0;
-    for (uint32_t r = q; r < a.hist_blocks; r += 4) f += a.partial[(uint64_t)r * 256 + col];
-    sm.part[q][col] = f;
-  }
+  if (tid < 256) sm.w[tid] = 0;
   if (tid == 0) sm.present = 0;
   __syncthreads();
-  if (tid < 256) {
-    sm.w[tid] = sm.part[0][tid] + sm.part[1][tid] + sm.part[2][tid] + sm.part[3][tid];
-    if (sm.w[tid]) atomicAdd(&sm.present, 1u);
+  {
+    // partial histograms: 64 column groups of 4 bins x 16 row groups, 16-byte
+    // loads, several in flight per thread
+    const uint32_t cg = tid & 63u;
+    uint64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    const uint4* p4 = reinterpret_cast<const uint4*>(a.partial);
+#pragma unroll 8
+    for (uint32_t r = tid >> 6; r < a.hist_blocks; r += 16) {
+      const uint4 v = p4[(uint64_t)r * 64 + cg];
+      s0 += v.x;
+      s1 += v.y;
+      s2 += v.z;
+      s3 += v.w;
+    }
+    atomicAdd(reinterpret_cast<unsigned long long*>(&sm.w[4 * cg]), (unsigned long long)s0);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&sm.w[4 * cg + 1]), (unsigned long long)s1);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&sm.w[4 * cg + 2]), (unsigned long long)s2);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&sm.w[4 * cg + 3]), (unsigned long long)s3);
   }
   __syncthreads();
+  if (tid < 256 && sm.w[tid]) atomicAdd(&sm.present, 1u);
+  __syncthreads();
   const uint32_t m = sm.present;
-  for (;;) {
+  // weights are at most 2^40, so 41 halvings make them all 1 and the tree at
+  // most 8 deep: the cap never binds for a correct build, it only guarantees
+  // that the loop ends
+  uint32_t rounds = 0;
+  for (;; ++rounds) {
+    // sort by rank: keys are distinct (absent symbols get distinct keys
+    // above every present one)
+    if (tid == 0) sm.total = 0;
     if (tid < 256) {
-      sm.key[tid] = sm.w[tid] ? (sm.w[tid] << 8 | tid) : ~0ull;
+      sm.tmp[tid] = sm.w[tid] ? (sm.w[tid] << 8 | tid) : (~0ull << 8 | tid);
       sm.len[tid] = 0;
     }
     __syncthreads();
-    // bitonic sort, ascending
-    for (uint32_t k = 2; k <= 256; k <<= 1) {
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        if (tid < 128) {
-          const uint32_t i = (tid / j) * (2 * j) + (tid % j), p = i + j;
-          const uint64_t x = sm.key[i], y = sm.key[p];
-          if ((x > y) == ((i & k) == 0)) {
-            sm.key[i] = y;
-            sm.key[p] = x;
-          }
-        }
-        __syncthreads();
-      }
+    if (tid < 256 && sm.w[tid]) atomicAdd(reinterpret_cast<unsigned long long*>(&sm.total),
+                                          (unsigned long long)sm.w[tid]);
+    if (tid < 256) {
+      const uint64_t k = sm.tmp[tid];
+      uint32_t r = 0;
+      for (uint32_t j = 0; j < 256; ++j) r += sm.tmp[j] < k;
+      sm.key[r] = k;
     }
+    __syncthreads();
     if (tid == 0) {
-      uint32_t deepest = 0;
+      uint32_t kc = 0;
       if (m == 1) {
         sm.len[sm.key[0] & 255u] = 1;
-        deepest = 1;
       } else if (m > 1) {
-        // Huffman's merge: the next node is the front leaf unless the front
-        // internal node is strictly lighter (a leaf wins ties: its index is
-        // smaller); internal nodes are made in nondecreasing weight order
-        uint32_t li = 0, kf = 0, kc = 0;
-        for (uint32_t s = 0; s + 1 < m; ++s) {
-          uint32_t node[2];
-          uint64_t wt[2];
-#pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            if (li < m && (kf == kc || (sm.key[li] >> 8) <= sm.iw[kf])) {
-              wt[t] = sm.key[li] >> 8;
-              node[t] = li++;
-            } else {
-              wt[t] = sm.iw[kf];
-              node[t] = 256 + kf++;
-            }
-          }
-          sm.iw[kc] = wt[0] + wt[1];
-          sm.parent[node[0]] = (uint16_t)(256 + kc);
-          sm.parent[node[1]] = (uint16_t)(256 + kc);
-          ++kc;
-        }
-        // depths: every node's parent is made after it
-        sm.depth[kc - 1] = 0;
-        for (int k = (int)kc - 2; k >= 0; --k) sm.depth[k] = sm.depth[sm.parent[256 + k] - 256] + 1;
-        for (uint32_t j = 0; j < m; ++j) {
-          const uint32_t d = sm.depth[sm.parent[j] - 256] + 1u;
-          sm.len[sm.key[j] & 255u] = (uint8_t)d;
-          deepest = d > deepest ? d : deepest;
-        }
+        // 32-bit weights while every weight stays below the 32-bit infinity
+        kc = sm.total >> 31 ? merge<uint64_t>(sm, m) : merge<uint32_t>(sm, m);
       }
-      sm.deepest = deepest;
+      sm.internal = kc;
+      sm.deepest = m == 1 ? 1u : 0u;
+    }
+    __syncthreads();
+    // depths of the internal nodes by pointer jumping (8 rounds cover 255)
+    const uint32_t kc = sm.internal;
+    if (tid < kc) {
+      const bool root = tid + 1 == kc;
+      sm.anc[tid] = (uint16_t)(root ? tid : sm.parent[256 + tid] - 256u);
+      sm.dist[tid] = root ? 0 : 1;
+    }
+    __syncthreads();
+    for (uint32_t round = 0; round < 8; ++round) {
+      uint32_t d = 0, na = 0;
+      if (tid < kc) {
+        const uint32_t up = sm.anc[tid];
+        d = sm.dist[tid] + sm.dist[up];
+        na = sm.anc[up];
+      }
+      __syncthreads();
+      if (tid < kc) {
+        sm.dist[tid] = (uint16_t)d;
+        sm.anc[tid] = (uint16_t)na;
+      }
+      __syncthreads();
+    }
+    if (kc && tid < m) {
+      const uint32_t d = sm.dist[sm.parent[tid] - 256u] + 1u;
+      sm.len[sm.key[tid] & 255u] = (uint8_t)d;
+      atomicMax(&sm.deepest, d);
     }
     __syncthreads();
     if (sm.deepest <= kLimit) break;
+    if (rounds == kMaxLimitRounds) {
+      if (tid == 0) a.codes[256] = 1;  // reported by scan_kernel
+      return;
+    }
     if (tid < 256) sm.w[tid] = (sm.w[tid] + 1) / 2;
     __syncthreads();
   }
@@ -181,12 +264,13 @@ __global__ __launch_bounds__(1024) void build_kernel(EncArgs a) {
     a.codes[tid] = l << 16 | code;
   }
   if (tid < 128) a.out[64 + tid] = (uint8_t)(sm.len[2 * tid] | sm.len[2 * tid + 1] << 4);
+  if (tid == 0) a.codes[256] = 0;
 }
 
 __global__ __launch_bounds__(256) void size_kernel(EncArgs a) {
   __shared__ uint32_t L[256];
   const uint64_t n = input_size(a);
-  if (n > a.max_n) return;
+  if (n > a.max_n || a.codes[256] != 0) return;
   const uint64_t N = chunks(n);
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   L[tid] = a.codes[tid] >> 16;
@@ -238,7 +322,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(EncArgs a) {
   __shared__ uint64_t scratch[1024 / 64 + 1];
   const uint64_t n = input_size(a);
   const uint32_t tid = threadIdx.x;
-  if (n > a.max_n) {
+  if (n > a.max_n || a.codes[256] != 0) {
     if (tid == 0) {
       *a.out_bytes = 0;
       *a.status = kInvalidArg;
@@ -256,77 +340,86 @@ __global__ __launch_bounds__(1024) void scan_kernel(EncArgs a) {
   if (tid < 64) a.out[tid] = header_byte(tid, n, N, total);
 }
 
-__global__ __launch_bounds__(256) void encode_kernel(EncArgs a) {
+// One wave per chunk, four chunks per workgroup. Lane l codes the chunk's
+// bytes [64 l, 64 l + 64): its bit count, a wave prefix sum (DPP) for its bit
+// offset, then its codes ORed into the wave's LDS words through a 64-bit
+// accumulator (only the first and last word of a lane's range are shared
+// with a neighbour). Sub-block k starts at lane 2k's offset.
+constexpr uint32_t kEncWaves = 4;
+
+struct EncWaveLds {
+  uint32_t words[kMaxWords];
+  uint32_t offs32[kSubs / 2 + 1];
+};
+
+__global__ __launch_bounds__(64 * kEncWaves) void encode_kernel(EncArgs a) {
   __shared__ uint32_t code[256];
-  __shared__ uint32_t words[kMaxWords];
-  __shared__ uint32_t offs32[kSubs / 2 + 1];
-  __shared__ uint32_t scratch[8];
+  __shared__ EncWaveLds wl[kEncWaves];
   const uint64_t n = input_size(a);
-  if (n > a.max_n) return;
+  if (n > a.max_n || a.codes[256] != 0) return;
   const uint64_t N = chunks(n);
-  const uint64_t i = blockIdx.x;
-  if (i >= N) return;
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   code[tid] = a.codes[tid];
+  __syncthreads();
+  const uint64_t i = (uint64_t)blockIdx.x * kEncWaves + wave;
+  if (i >= N) return;
+  EncWaveLds& w = wl[wave];
   const uint64_t first = i * kChunk;
   const uint32_t c = (uint32_t)(n - first < kChunk ? n - first : kChunk);
   const uint32_t nsub = (c + kSub - 1) / kSub;
-  // this thread's 16 symbols
-  const uint32_t j0 = 16 * tid;
-  const uint32_t cnt = j0 < c ? (c - j0 < 16 ? c - j0 : 16) : 0;
-  uint4 q = make_uint4(0, 0, 0, 0);
-  if (cnt == 16) {
-    q = reinterpret_cast<const uint4*>(a.in + first)[tid];
+  // this lane's 64 bytes
+  const uint32_t j0 = 64 * lane;
+  const uint32_t cnt = j0 < c ? (c - j0 < 64 ? c - j0 : 64) : 0;
+  uint4 q[4];
+  if (cnt == 64) {
+    const uint4* in4 = reinterpret_cast<const uint4*>(a.in + first + j0);
+#pragma unroll
+    for (uint32_t v = 0; v < 4; ++v) q[v] = in4[v];
   } else {
-    uint32_t v[4] = {0, 0, 0, 0};
-    for (uint32_t b = 0; b < cnt; ++b) v[b >> 2] |= (uint32_t)a.in[first + j0 + b] << (8 * (b & 3));
-    q = make_uint4(v[0], v[1], v[2], v[3]);
+    uint32_t t[16];
+#pragma unroll
+    for (uint32_t v = 0; v < 16; ++v) t[v] = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < 64; ++b)
+      if (b < cnt) t[b >> 2] |= (uint32_t)a.in[first + j0 + b] << (8 * (b & 3));
+#pragma unroll
+    for (uint32_t v = 0; v < 4; ++v) q[v] = make_uint4(t[4 * v], t[4 * v + 1], t[4 * v + 2], t[4 * v + 3]);
   }
-  __syncthreads();
   uint32_t mybits = 0;
 #pragma unroll
-  for (uint32_t b = 0; b < 16; ++b) mybits += b < cnt ? code[byte_of(q, b)] >> 16 : 0u;
-  // block-wide exclusive scan of the bit counts
-  const uint32_t lane = tid & 63u, wid = tid >> 6;
+  for (uint32_t b = 0; b < 64; ++b) mybits += b < cnt ? code[byte_of(q[b >> 4], b & 15u)] >> 16 : 0u;
   const uint32_t incl = wave_incl_scan(mybits);
-  if (lane == 63) scratch[wid] = incl;
-  __syncthreads();
-  uint32_t before = 0, total = 0;
-#pragma unroll
-  for (uint32_t w = 0; w < 4; ++w) {
-    before += w < wid ? scratch[w] : 0u;
-    total += scratch[w];
-  }
-  const uint32_t off = before + incl - mybits;
-  uint16_t* offs16 = reinterpret_cast<uint16_t*>(offs32);
-  if ((tid & 7u) == 0 && j0 < c) offs16[tid >> 3] = (uint16_t)off;  // sub-block tid / 8 starts here
-  if (tid == 0 && (nsub & 1u)) offs16[nsub] = 0;
+  const uint32_t off = incl - mybits;
+  const uint32_t total = readlane(incl, 63);
+  uint16_t* offs16 = reinterpret_cast<uint16_t*>(w.offs32);
+  if ((lane & 1u) == 0 && j0 < c) offs16[lane >> 1] = (uint16_t)off;  // sub-block lane / 2
+  if (lane == 0 && (nsub & 1u)) offs16[nsub] = 0;
   const uint32_t nwords = (total + 31) / 32;
-  for (uint32_t k = tid; k < nwords; k += 256) words[k] = 0;
-  __syncthreads();
-  // codes into the words: a 64-bit accumulator whose top `used` bits are
-  // taken; full top words are ORed into LDS (only the first and last word
-  // of a thread's range are shared with a neighbour)
+  for (uint32_t k = lane; k < nwords; k += 64) w.words[k] = 0;
+  wave_sync();
   if (cnt) {
     uint64_t acc = 0;
     uint32_t used = off & 31u, wi = off >> 5;
-    for (uint32_t b = 0; b < cnt; ++b) {
-      const uint32_t e = code[byte_of(q, b)];
-      const uint32_t l = e >> 16;
-      acc |= (uint64_t)(e & 0xFFFFu) << (64 - used - l);
-      used += l;
-      if (used >= 32) {
-        atomicOr(&words[wi++], (uint32_t)(acc >> 32));
-        acc <<= 32;
-        used -= 32;
+#pragma unroll
+    for (uint32_t b = 0; b < 64; ++b) {
+      if (b < cnt) {
+        const uint32_t e = code[byte_of(q[b >> 4], b & 15u)];
+        const uint32_t l = e >> 16;
+        acc |= (uint64_t)(e & 0xFFFFu) << (64 - used - l);
+        used += l;
+        if (used >= 32) {
+          atomicOr(&w.words[wi++], (uint32_t)(acc >> 32));
+          acc <<= 32;
+          used -= 32;
+        }
       }
     }
-    if (used) atomicOr(&words[wi], (uint32_t)(acc >> 32));
+    if (used) atomicOr(&w.words[wi], (uint32_t)(acc >> 32));
   }
-  __syncthreads();
+  wave_sync();
   const uint32_t ow = offsets_bytes(nsub) / 4;
   uint32_t* rec = reinterpret_cast<uint32_t*>(a.out + kPre + 4 * N + a.offs[i]);
-  for (uint32_t k = tid; k < ow + nwords; k += 256) rec[k] = k < ow ? offs32[k] : words[k - ow];
+  for (uint32_t k = lane; k < ow + nwords; k += 64) rec[k] = k < ow ? w.offs32[k] : w.words[k - ow];
 }
 
 // ---- decompression ---------------------------------------------------------
@@ -399,15 +492,31 @@ __global__ __launch_bounds__(1024) void dec_prepare_kernel(DecArgs a) {
     return;
   }
   for (uint32_t k = tid; k < (1u << kLutBits); k += 1024) T.lut[k] = 0;
+  for (uint32_t k = tid; k < kMaxSubtables * 16; k += 1024) T.lut2[k] = 0;
   __syncthreads();
   if (tid < 256 && sm.len[tid]) {
     const uint32_t l = sm.len[tid];
     uint32_t r = 0;
     for (uint32_t t = 0; t < tid; ++t) r += sm.len[t] == l;
     T.by_rank[T.rank0[l] + r] = (uint8_t)tid;
+    const uint32_t code = T.first[l] + r;
     if (l <= kLutBits) {
-      const uint32_t base = (T.first[l] + r) << (kLutBits - l);
+      const uint32_t base = code << (kLutBits - l);
       for (uint32_t k = 0; k < (1u << (kLutBits - l)); ++k) T.lut[base + k] = (uint16_t)(l << 8 | tid);
+    } else {
+      // long codes follow every shorter one, so their 11-bit prefixes run
+      // consecutively from first[12] / 2 (the start of length 12, left-justified)
+      const uint32_t p0 = T.first[kLutBits + 1] >> 1;
+      const uint32_t base = code << (kLimit - l);  // 15-bit left-justified
+      for (uint32_t k = 0; k < (1u << (kLimit - l)); ++k) {
+        const uint32_t v = base + k, t = (v >> 4) - p0;
+        if (t < kMaxSubtables) {
+          T.lut[v >> 4] = (uint16_t)(0x8000u | t);
+          T.lut2[t * 16 + (v & 15u)] = (uint16_t)(l << 8 | tid);
+        } else {
+          sm.bad = 1;
+        }
+      }
     }
   }
   // record sizes from the table of code bits
@@ -438,118 +547,150 @@ __global__ __launch_bounds__(1024) void dec_prepare_kernel(DecArgs a) {
   for (uint32_t k = tid; k < sizeof(DecTables) / 4; k += 1024) dst[k] = src[k];
 }
 
-constexpr uint32_t kGroupChunks = 8;                  // chunks per decode workgroup (2 per wave)
-constexpr uint32_t kStageSub = kSub + 4;              // LDS bytes per sub-block (bank padding)
+constexpr uint32_t kDecWaves = 4;                  // waves per decode workgroup
+constexpr uint32_t kInStageWords = 1024;           // code words staged per chunk (8 bits/symbol)
+constexpr uint32_t kStageSub = kSub + 4;           // LDS bytes per decoded sub-block (bank padding)
 constexpr uint32_t kStageChunk = kSubs * kStageSub + 4;
-constexpr uint32_t kDecodeBlocks = 256 * 4;
+constexpr uint32_t kDecodeBlocks = 256 * 2;
+
+struct DecWaveLds {
+  uint32_t in[2][kInStageWords];       // code words of the wave's two chunks
+  uint32_t out[2][kStageChunk / 4];    // their decoded bytes
+};
 
 struct DecLds {
   uint16_t lut[1u << kLutBits];
-  uint32_t first[16], count[16], rank0[16];
-  uint8_t by_rank[256];
-  uint32_t stage[kGroupChunks * kStageChunk / 4];
+  uint16_t lut2[kMaxSubtables * 16];
+  DecWaveLds w[kDecWaves];
 };
 
-__global__ __launch_bounds__(256) void decode_kernel(DecArgs a) {
+struct DecCode {
+  const uint16_t* lut;
+  const uint16_t* lut2;
+};
+
+// Decodes the `cnt` symbols of one sub-block starting at bit `start` of the
+// chunk's code words `wds` (nwords >= 1 of them) into `out32`; returns the
+// bit position after them, or ~0u if one of them matches no code. Every lane
+// runs all 128 steps, so the loop is uniform across the wave: steps past
+// `cnt` decode whatever bits follow and are ignored (they only write into
+// this sub-block's own stage slot). Word reads are clamped to the last word
+// instead of branching: bits past a sub-block's end never decide whether it
+// ends exactly at its end bit. The bit buffer is refilled once per pair of
+// symbols (after a refill it holds at least 32 bits; two codes take at most
+// 30). Codes of up to 11 bits take one table read, longer ones a second one.
+template <typename WordPtr>
+__device__ __forceinline__ uint32_t decode_sub(const DecCode& dc, WordPtr wds, uint32_t nwords,
+                                               uint32_t start, uint32_t cnt, uint32_t* out32) {
+  const uint32_t last = nwords - 1;
+  uint32_t wi = start >> 5;
+  const uint32_t w0 = wds[wi < last ? wi : last], w1 = wds[wi + 1 < last ? wi + 1 : last];
+  wi += 2;
+  uint64_t buf = ((uint64_t)w0 << 32 | w1) << (start & 31u);
+  uint32_t avail = 64 - (start & 31u), p = start, p_end = start;
+  bool bad = false;
+  for (uint32_t j = 0; j < kSub; j += 4) {
+    uint32_t acc = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) {
+      if ((u & 1u) == 0) {
+        const uint32_t w = wds[wi < last ? wi : last];
+        const bool take = avail < 32;
+        buf |= take ? (uint64_t)w << (32 - avail) : 0ull;
+        wi += take ? 1u : 0u;
+        avail += take ? 32u : 0u;
+      }
+      const uint32_t peek = (uint32_t)(buf >> (64 - kLimit));
+      uint32_t e = dc.lut[peek >> (kLimit - kLutBits)];
+      if (e & 0x8000u) e = dc.lut2[(e & 0x7FFFu) * 16 + (peek & 15u)];
+      uint32_t l = e >> 8;
+      const uint32_t sym = e & 0xFFu;
+      if (l == 0) bad = bad || j + u < cnt;
+      l = l ? l : 1u;
+      buf <<= l;
+      avail -= l;
+      p += l;
+      p_end = j + u + 1 == cnt ? p : p_end;
+      acc |= sym << (8 * u);
+    }
+    out32[j >> 2] = acc;
+  }
+  return bad ? ~0u : p_end;
+}
+
+// Each wave takes two chunks at a time (32 lanes each, one lane per
+// 128-symbol sub-block): it stages the chunks' code words in LDS with
+// coalesced loads, decodes every sub-block from LDS into an LDS stage, and
+// writes the chunks out with consecutive 4-byte stores. Only the wave
+// synchronises; a chunk with more than 4 KiB of code words (above 8 bits per
+// symbol) is decoded from global memory instead.
+__global__ __launch_bounds__(64 * kDecWaves) void decode_kernel(DecArgs a) {
   __shared__ DecLds sm;
   const DecTables* T = a.tab;
   if (T->status != kOk) return;
-  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint64_t n = T->n, N = T->N;
-  for (uint32_t k = tid; k < (1u << kLutBits); k += 256) sm.lut[k] = T->lut[k];
-  if (tid < 16) {
-    sm.first[tid] = T->first[tid];
-    sm.count[tid] = T->count[tid];
-    sm.rank0[tid] = T->rank0[tid];
-  }
-  sm.by_rank[tid] = T->by_rank[tid];
+  for (uint32_t k = tid; k < (1u << kLutBits); k += 64 * kDecWaves) sm.lut[k] = T->lut[k];
+  for (uint32_t k = tid; k < kMaxSubtables * 16; k += 64 * kDecWaves) sm.lut2[k] = T->lut2[k];
+  DecCode dc;
+  dc.lut = sm.lut;
+  dc.lut2 = sm.lut2;
   __syncthreads();
   const uint32_t* bits_tab = reinterpret_cast<const uint32_t*>(a.in + kPre);
   const uint64_t rec_base = kPre + 4 * N;
-  uint8_t* stage8 = reinterpret_cast<uint8_t*>(sm.stage);
-  for (uint64_t g = blockIdx.x; g * kGroupChunks < N; g += gridDim.x) {
-    const uint32_t slot = 2 * (tid >> 6) + (lane >> 5);
-    const uint32_t k = lane & 31u;
-    const uint64_t i = g * kGroupChunks + slot;
-    bool bad = false;
-    if (i < N) {
-      const uint32_t c = (uint32_t)(n - i * kChunk < kChunk ? n - i * kChunk : kChunk);
-      const uint32_t nsub = (c + kSub - 1) / kSub;
-      if (k < nsub) {
-        const uint8_t* rec = a.in + rec_base + a.offs[i];
-        const uint16_t* o16 = reinterpret_cast<const uint16_t*>(rec);
-        const uint32_t bits = bits_tab[i];
-        const uint32_t nwords = (bits + 31) / 32;
-        const uint32_t* wds = reinterpret_cast<const uint32_t*>(rec + offsets_bytes(nsub));
-        const uint32_t start = o16[k];
-        const uint32_t end = k + 1 < nsub ? o16[k + 1] : bits;
-        const uint32_t cnt = k + 1 < nsub ? kSub : c - kSub * k;
-        if ((k == 0 && start != 0) || end > bits || start > end) bad = true;
-        if (k + 1 == nsub && (nsub & 1u) && o16[nsub] != 0) bad = true;
-        if (k + 1 == nsub && (bits & 31u) && (wds[nwords - 1] << (bits & 31u)) != 0) bad = true;
-        if (!bad) {
-          uint32_t wi = start >> 5;
-          const uint32_t w0 = wi < nwords ? wds[wi] : 0u, w1 = wi + 1 < nwords ? wds[wi + 1] : 0u;
-          uint64_t buf = ((uint64_t)w0 << 32 | w1) << (start & 31u);
-          uint32_t avail = 64 - (start & 31u), p = start;
-          wi += 2;
-          uint32_t acc = 0;
-          uint32_t* out32 = reinterpret_cast<uint32_t*>(stage8 + slot * kStageChunk + k * kStageSub);
-          for (uint32_t j = 0; j < cnt; ++j) {
-            if (avail < 32) {
-              buf |= (uint64_t)(wi < nwords ? wds[wi] : 0u) << (32 - avail);
-              ++wi;
-              avail += 32;
-            }
-            const uint32_t peek = (uint32_t)(buf >> (64 - kLimit));
-            const uint32_t e = sm.lut[peek >> (kLimit - kLutBits)];
-            uint32_t l = e >> 8, s = e & 0xFFu;
-            if (l == 0) {
-              uint32_t v = 0;
-              for (l = kLutBits + 1; l <= kLimit; ++l) {
-                v = peek >> (kLimit - l);
-                if (v - sm.first[l] < sm.count[l]) break;
-              }
-              if (l > kLimit) {
-                bad = true;
-                break;
-              }
-              s = sm.by_rank[sm.rank0[l] + v - sm.first[l]];
-            }
-            buf <<= l;
-            avail -= l;
-            p += l;
-            acc |= s << (8 * (j & 3u));
-            if ((j & 3u) == 3u) {
-              out32[j >> 2] = acc;
-              acc = 0;
-            }
-          }
-          if (!bad && (cnt & 3u)) out32[cnt >> 2] = acc;
-          if (p != end) bad = true;
+  DecWaveLds& w = sm.w[wave];
+  const uint32_t half = lane >> 5, k = lane & 31u;
+  uint8_t* out8 = reinterpret_cast<uint8_t*>(w.out[half]);
+  bool bad = false;
+  for (uint64_t g = (uint64_t)blockIdx.x * kDecWaves + wave; 2 * g < N; g += (uint64_t)gridDim.x * kDecWaves) {
+    const uint64_t i = 2 * g + half;
+    const bool live = i < N;
+    uint32_t c = 0, nsub = 0, bits = 0, nwords = 0;
+    const uint8_t* rec = nullptr;
+    const uint32_t* wds = nullptr;
+    if (live) {
+      c = (uint32_t)(n - i * kChunk < kChunk ? n - i * kChunk : kChunk);
+      nsub = (c + kSub - 1) / kSub;
+      rec = a.in + rec_base + a.offs[i];
+      bits = bits_tab[i];
+      nwords = (bits + 31) / 32;
+      wds = reinterpret_cast<const uint32_t*>(rec + offsets_bytes(nsub));
+    }
+    const bool staged = nwords <= kInStageWords;
+    if (live && staged)
+      for (uint32_t q = k; q < nwords; q += 32) w.in[half][q] = wds[q];
+    wave_sync();
+    if (live && k < nsub) {
+      const uint16_t* o16 = reinterpret_cast<const uint16_t*>(rec);
+      const uint32_t start = o16[k];
+      const uint32_t end = k + 1 < nsub ? o16[k + 1] : bits;
+      const uint32_t cnt = k + 1 < nsub ? kSub : c - kSub * k;
+      bool ok = !((k == 0 && start != 0) || end > bits || start > end || bits == 0);
+      if (k + 1 == nsub && (nsub & 1u) && o16[nsub] != 0) ok = false;
+      if (ok && k + 1 == nsub && (bits & 31u) && (wds[nwords - 1] << (bits & 31u)) != 0) ok = false;
+      if (ok) {
+        uint32_t* out32 = reinterpret_cast<uint32_t*>(out8 + k * kStageSub);
+        const uint32_t p = staged ? decode_sub(dc, (const uint32_t*)w.in[half], nwords, start, cnt, out32)
+                                  : decode_sub(dc, wds, nwords, start, cnt, out32);
+        ok = p == end;
+      }
+      bad = bad || !ok;
+    }
+    wave_sync();
+    if (live) {
+      uint8_t* dst = a.out + i * kChunk;
+      for (uint32_t p = 4 * k; p < c; p += 4 * 32) {
+        const uint32_t v = *reinterpret_cast<const uint32_t*>(out8 + (p / kSub) * kStageSub + p % kSub);
+        if (p + 4 <= c) {
+          *reinterpret_cast<uint32_t*>(dst + p) = v;
+        } else {
+          for (uint32_t b = 0; p + b < c; ++b) dst[p + b] = (uint8_t)(v >> (8 * b));
         }
       }
     }
-    __syncthreads();
-    // staged chunks to the output, 4 bytes per store
-    for (uint32_t q = tid; q < kGroupChunks * kChunk / 4; q += 256) {
-      const uint32_t s = q / (kChunk / 4), p = 4 * (q % (kChunk / 4));
-      const uint64_t ci = g * kGroupChunks + s;
-      if (ci >= N) break;
-      const uint32_t c = (uint32_t)(n - ci * kChunk < kChunk ? n - ci * kChunk : kChunk);
-      if (p >= c) continue;
-      const uint32_t v =
-          *reinterpret_cast<const uint32_t*>(stage8 + s * kStageChunk + (p / kSub) * kStageSub + p % kSub);
-      uint8_t* dst = a.out + ci * kChunk + p;
-      if (p + 4 <= c) {
-        *reinterpret_cast<uint32_t*>(dst) = v;
-      } else {
-        for (uint32_t b = 0; p + b < c; ++b) dst[b] = (uint8_t)(v >> (8 * b));
-      }
-    }
-    if (bad) atomicExch(a.status, kCorrupt);
-    __syncthreads();
+    wave_sync();
   }
+  if (bad) atomicExch(a.status, kCorrupt);
 }
 
 }  // namespace
@@ -560,13 +701,14 @@ hipError_t launch_compress(const EncArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(build_kernel, dim3(1), dim3(1024), 0, s, a);
   if (N) hipLaunchKernelGGL(size_kernel, dim3((uint32_t)((N + 3) / 4)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, a);
-  if (N) hipLaunchKernelGGL(encode_kernel, dim3((uint32_t)N), dim3(256), 0, s, a);
+  if (N) hipLaunchKernelGGL(encode_kernel, dim3((uint32_t)((N + kEncWaves - 1) / kEncWaves)),
+                           dim3(64 * kEncWaves), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_decompress(const DecArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(dec_prepare_kernel, dim3(1), dim3(1024), 0, s, a);
-  hipLaunchKernelGGL(decode_kernel, dim3(kDecodeBlocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(decode_kernel, dim3(kDecodeBlocks), dim3(64 * kDecWaves), 0, s, a);
   return hipGetLastError();
 }
 

@@ -22,9 +22,13 @@ constexpr uint32_t kSub = 128;               // symbols per sub-block
 constexpr uint32_t kSubs = kChunk / kSub;    // sub-blocks per full chunk
 constexpr uint32_t kLimit = 15;              // longest code
 constexpr uint32_t kLutBits = 11;            // decoder lookup table index bits
+// Codes longer than 11 bits cover at most 256 x 8 fifteen-bit slots, i.e. 128
+// eleven-bit prefixes (129 when unaligned): the second-level subtables.
+constexpr uint32_t kMaxSubtables = 136;
 constexpr uint32_t kPre = 192;               // header + code lengths
 constexpr uint32_t kMaxWords = (kChunk * kLimit + 31) / 32;  // code words of a full chunk
 constexpr uint32_t kMaxHistBlocks = 512;
+constexpr uint32_t kMaxLimitRounds = 48;     // cap on rebuilds by the length limit
 constexpr uint64_t kMaxInput = 1ull << 40;
 
 __host__ __device__ inline uint64_t chunks(uint64_t n) { return (n + kChunk - 1) / kChunk; }
@@ -40,7 +44,8 @@ __host__ inline uint32_t hist_blocks(uint64_t max_n) {
   return (uint32_t)(b < 1 ? 1 : b > kMaxHistBlocks ? kMaxHistBlocks : b);
 }
 
-// Compress workspace: partial histograms | code table | record sizes (u32
+// Compress workspace: partial histograms | code table (256 codes + a build
+// status word) | record sizes (u32
 // pairs: sub-block offset bytes, code word bytes) | record offsets (N + 1).
 struct EncWorkspace {
   uint64_t partial_off, codes_off, sizes_off, offs_off, total;
@@ -51,7 +56,7 @@ __host__ inline EncWorkspace enc_workspace(uint64_t max_n) {
   EncWorkspace w;
   w.partial_off = 0;
   w.codes_off = align_up(4ull * 256 * hist_blocks(max_n), 256);
-  w.sizes_off = w.codes_off + 1024;
+  w.sizes_off = w.codes_off + 2048;
   w.offs_off = w.sizes_off + align_up(8 * N, 256);
   w.total = w.offs_off + align_up(8 * (N + 1), 256);
   return w;
@@ -63,7 +68,7 @@ struct EncArgs {
   const uint64_t* d_n;  // device-resident input size (optional)
   uint32_t hist_blocks;
   uint32_t* partial;    // hist_blocks x 256
-  uint32_t* codes;      // 256 x (length << 16 | code)
+  uint32_t* codes;      // 256 x (length << 16 | code), then the build status
   uint32_t* sizes;      // 2 per chunk
   uint64_t* offs;       // N + 1
   uint8_t* out;
@@ -80,7 +85,11 @@ struct DecTables {
   uint32_t count[16];  // codes of each length
   uint32_t rank0[16];  // rank of the first code of each length
   uint8_t by_rank[256];
-  uint16_t lut[1u << kLutBits];  // 11-bit prefix -> length << 8 | symbol (0: longer code)
+  // two-level decoding table: lut[11-bit prefix] = length << 8 | symbol for
+  // codes of up to 11 bits, 0x8000 | t for a prefix of longer codes (t-th
+  // 16-entry subtable of lut2, indexed by the next 4 bits), 0 for no code
+  uint16_t lut[1u << kLutBits];
+  uint16_t lut2[kMaxSubtables * 16];
 };
 
 // Decompress workspace: tables | record sizes (u32 pairs) | record offsets.

@@ -49,6 +49,9 @@ def _inputs():
     while len(fib) < 18:
         fib.append(fib[-1] + fib[-2])
     yield "length_limit", b"".join(bytes([s]) * f for s, f in enumerate(fib))
+    # counts 2^17 .. 2^0 and 22 singletons: code lengths 11 through 15 (the
+    # two-level decoding table)
+    yield "long_codes", b"".join(bytes([s]) * (1 << (17 - s)) for s in range(18)) + bytes(range(18, 40))
     x = synth.laplace_codes(1 << 19, seed=4)
     yield "lz_stream_of_codes", oracle.compress(x, 2, 2048, 128, 2)
 
