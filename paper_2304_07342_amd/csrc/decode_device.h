@@ -334,6 +334,12 @@ __device__ bool decode_chunk_block(const uint8_t* rec, const uint8_t* in_end, ui
   uint32_t tot;
   const uint32_t x1 = waves_excl((nh - np) | (np << 16), sm.scratch, tot);
   const uint32_t lit0 = x1 & 0xFFFFu, ptr0 = x1 >> 16;
+  // Pointer symbols are resolved in parallel (pointer jumping, below) when the
+  // chunk has many pointers and its decoded bytes leave room in `out` for a
+  // 16-bit source index per symbol; otherwise wave 0 copies them in order.
+  const uint32_t src_at = (c * S + 15) & ~15u;
+  const bool jump = (tot >> 16) >= 64 && src_at + 2 * c <= kFastOut;
+  uint16_t* src = reinterpret_cast<uint16_t*>(sm.out + src_at);
 
   // this wave's total length: one per token, plus L - 1 per pointer whose
   // payload is in range
@@ -391,13 +397,17 @@ __device__ bool decode_chunk_block(const uint8_t* rec, const uint8_t* in_end, ui
         if (!okp) {
           bad = true;
         } else if (isp) {
-          bad = bad || !(L >= MIN && O <= W && O <= pos && L <= O && pos + L <= c);
+          const bool ok = L >= MIN && O <= W && O <= pos && L <= O && pos + L <= c;
+          bad = bad || !ok;
+          if (ok && jump)
+            for (uint32_t k = 0; k < L; ++k) src[pos + k] = (uint16_t)(pos + k - O);
         } else {
           out[pos] = load_sym<S>(pay + off);
+          if (jump) src[pos] = (uint16_t)pos;
         }
       }
       const uint64_t tb = ballot(tk && isp);
-      if (lane == 0) sm.ptrbits[16 * wave + j] = tb;
+      if (lane == 0 && !jump) sm.ptrbits[16 * wave + j] = tb;
       lit += popc64(lm);
       ptr += popc64(pmj);
     }
@@ -410,11 +420,39 @@ __device__ bool decode_chunk_block(const uint8_t* rec, const uint8_t* in_end, ui
   if (bad || pos_end < c || (Tn + 7) / 8 != F || uend != P) return false;
   if (Tn < nt && (fl[F - 1] >> (Tn - 8 * (F - 1))) != 0) return false;
 
+  // pointers. Symbol p of a pointer with offset O takes the value of symbol
+  // p - O (always earlier, since O <= its position), which is a literal or
+  // again a pointer symbol. Replacing every source by its source's source
+  // (pointer jumping) reaches a literal for every symbol within
+  // ceil(log2 c) <= 12 rounds: a chain of any length halves each round. The
+  // update is in place: a thread that reads an entry another thread just
+  // replaced still gets an earlier symbol of the same chain. Then every
+  // pointer symbol copies its literal.
+  if (jump) {
+    for (uint32_t round = 0; round < 13; ++round) {
+      bool changed = false;
+      for (uint32_t p = tid; p < c; p += kDecThreads) {
+        const uint32_t s0 = src[p];
+        const uint32_t s1 = src[s0];
+        if (s1 != s0) {
+          src[p] = (uint16_t)s1;
+          changed = true;
+        }
+      }
+      if (!__syncthreads_or(changed)) break;
+    }
+    for (uint32_t p = tid; p < c; p += kDecThreads) {
+      const uint32_t s0 = src[p];
+      if (s0 != p) out[p] = out[s0];
+    }
+    __syncthreads();
+  }
+
   // pointers, 64 at a time in token order, by wave 0. A pointer is copied
   // once the last uncopied pointer before it ends at or before its source
   // starts (destinations are ordered, so no uncopied output overlaps its
   // source); the first uncopied pointer always qualifies.
-  if (wave == 0) {
+  if (!jump && wave == 0) {
     const uint32_t nwd = (Tn + 63) / 64;
     const uint64_t wd = lane < nwd ? sm.ptrbits[lane] : 0ull;
     const uint32_t cnt = popc64(wd);
