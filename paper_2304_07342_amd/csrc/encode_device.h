@@ -345,6 +345,105 @@ struct CandCursor {
   }
 };
 
+// The exact longest match at candidate h (h >= 1): L << 9 | d (offset d),
+// or 0 if it is shorter than MIN. All 64 lanes take part; the result is
+// wave-uniform. Lanes hold offsets (d = 64 col + lane + 1); ties go to the
+// largest offset.
+template <int S, int WC>
+__device__ __forceinline__ uint32_t search_token(const typename SymType<S>::T* win, uint32_t h,
+                                                 uint32_t c, uint32_t W, uint32_t MIN,
+                                                 const uint64_t (&wmask)[WC], uint32_t lane) {
+  using T = typename SymType<S>::T;
+  if constexpr (kRunSearch<S>) {
+    const uint32_t key = match_key<S, WC>(win, h, min(kMaxMatch, c - h), W, lane);
+    return (key >> 9) >= MIN ? key : 0u;
+  } else {
+    // exact longest match at h. Invariant: A holds the offsets d >= L whose
+    // match at h is at least L long; extending to L + 1 drops d = L and keeps
+    // the offsets that also match at h + L. Rows come four per LDS round trip
+    // from one per-lane base address (positions up to 3 past the chunk end
+    // read slack bytes and are never used).
+    uint64_t A[WC];
+    if (h < 64u * WC) {
+#pragma unroll
+      for (int col = 0; col < WC; ++col) A[col] = wmask[col] & ballot(64u * col + lane + 1u <= h);
+    } else {
+#pragma unroll
+      for (int col = 0; col < WC; ++col) A[col] = wmask[col];
+    }
+    uint32_t L = 0;
+    const uint32_t lim = min(kMaxMatch, c - h);
+    while (L < lim) {
+      const uint32_t qb = h + L;
+      // this lane's window symbol for row r, column col: win[qb + r - (64 col + lane + 1)]
+      const T* wbase = win + (int)qb - (int)lane - 1 - 64 * (WC - 1);
+      T xr[4], wr[4][WC];
+      if constexpr (S <= 2) {
+        const auto xv = load4_sub<S>(win + qb);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xr[r] = (T)(xv >> (8 * S * r));
+#pragma unroll
+        for (int col = 0; col < WC; ++col) {
+          const auto wv = load4_sub<S>(wbase + 64 * (WC - 1 - col));
+#pragma unroll
+          for (int r = 0; r < 4; ++r) wr[r][col] = (T)(wv >> (8 * S * r));
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          xr[r] = win[qb + r];
+#pragma unroll
+          for (int col = 0; col < WC; ++col) wr[r][col] = wbase[r + 64 * (WC - 1 - col)];
+        }
+      }
+      if (L + 4 <= 64) {
+        // offsets d <= L (only d = L can still be present) all sit in column 0
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (L >= lim) goto found;
+          uint64_t B[WC];
+#pragma unroll
+          for (int col = 0; col < WC; ++col) B[col] = A[col] & ballot(wr[r][col] == xr[r]);
+          B[0] &= ~0ull << L;
+          uint64_t any = 0;
+#pragma unroll
+          for (int col = 0; col < WC; ++col) any |= B[col];
+          if (!any) goto found;
+#pragma unroll
+          for (int col = 0; col < WC; ++col) A[col] = B[col];
+          ++L;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (L >= lim) goto found;
+          uint64_t B[WC];
+          uint64_t any = 0;
+#pragma unroll
+          for (int col = 0; col < WC; ++col) {
+            const int sh = (int)L - 64 * col;  // offsets d <= L are too short
+            const uint64_t cap = sh <= 0 ? ~0ull : (sh >= 64 ? 0ull : (~0ull << sh));
+            B[col] = A[col] & ballot(wr[r][col] == xr[r]) & cap;
+            any |= B[col];
+          }
+          if (!any) goto found;
+#pragma unroll
+          for (int col = 0; col < WC; ++col) A[col] = B[col];
+          ++L;
+        }
+      }
+    }
+  found:
+    if (L < MIN) return 0u;
+    uint32_t d = 0;
+#pragma unroll
+    for (int col = WC - 1; col >= 0; --col) {
+      if (d == 0 && A[col]) d = 64u * col + 64u - (uint32_t)__clzll(A[col]);
+    }
+    return L << 9 | d;
+  }
+}
+
 // Encodes one chunk into its scratch slot and writes {F, P} to job.sizes.
 // Every wave of the workgroup stages the chunk and builds the hit bitmap;
 // waves other than 0 return after that, wave 0 parses and encodes.
@@ -416,106 +515,14 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
     }
     if (h >= c) break;
 
+    const uint32_t key = search_token<S, WC>(win, h, c, job.W, job.MIN, wmask, lane);
     uint32_t val;
-    if constexpr (kRunSearch<S>) {
-      const uint32_t key = match_key<S, WC>(win, h, min(kMaxMatch, c - h), job.W, lane);
-      const uint32_t L = key >> 9;
-      if (L >= job.MIN) {
-        val = 1u | (L << 1) | ((key & 0xFFu) << 9);
-        p = h + L;
-      } else {
-        val = h << 1;
-        p = h + 1;
-      }
+    if (key) {
+      val = 1u | ((key >> 9) << 1) | ((key & 0xFFu) << 9);
+      p = h + (key >> 9);
     } else {
-      // exact longest match at h. Invariant: A holds the offsets d >= L whose
-      // match at h is at least L long; extending to L + 1 drops d = L and keeps
-      // the offsets that also match at h + L. Rows come four per LDS round trip
-      // from one per-lane base address (positions up to 3 past the chunk end
-      // read slack bytes and are never used).
-      uint64_t A[WC];
-      if (h < 64u * WC) {
-#pragma unroll
-        for (int col = 0; col < WC; ++col) A[col] = wmask[col] & ballot(64u * col + lane + 1u <= h);
-      } else {
-#pragma unroll
-        for (int col = 0; col < WC; ++col) A[col] = wmask[col];
-      }
-      uint32_t L = 0;
-      const uint32_t lim = min(kMaxMatch, c - h);
-      while (L < lim) {
-        const uint32_t qb = h + L;
-        // this lane's window symbol for row r, column col: win[qb + r - (64 col + lane + 1)]
-        const T* wbase = win + (int)qb - (int)lane - 1 - 64 * (WC - 1);
-        T xr[4], wr[4][WC];
-        if constexpr (S <= 2) {
-          const auto xv = load4_sub<S>(win + qb);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) xr[r] = (T)(xv >> (8 * S * r));
-#pragma unroll
-          for (int col = 0; col < WC; ++col) {
-            const auto wv = load4_sub<S>(wbase + 64 * (WC - 1 - col));
-#pragma unroll
-            for (int r = 0; r < 4; ++r) wr[r][col] = (T)(wv >> (8 * S * r));
-          }
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            xr[r] = win[qb + r];
-#pragma unroll
-            for (int col = 0; col < WC; ++col) wr[r][col] = wbase[r + 64 * (WC - 1 - col)];
-          }
-        }
-        if (L + 4 <= 64) {
-          // offsets d <= L (only d = L can still be present) all sit in column 0
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            if (L >= lim) goto found;
-            uint64_t B[WC];
-#pragma unroll
-            for (int col = 0; col < WC; ++col) B[col] = A[col] & ballot(wr[r][col] == xr[r]);
-            B[0] &= ~0ull << L;
-            uint64_t any = 0;
-#pragma unroll
-            for (int col = 0; col < WC; ++col) any |= B[col];
-            if (!any) goto found;
-#pragma unroll
-            for (int col = 0; col < WC; ++col) A[col] = B[col];
-            ++L;
-          }
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            if (L >= lim) goto found;
-            uint64_t B[WC];
-            uint64_t any = 0;
-#pragma unroll
-            for (int col = 0; col < WC; ++col) {
-              const int sh = (int)L - 64 * col;  // offsets d <= L are too short
-              const uint64_t cap = sh <= 0 ? ~0ull : (sh >= 64 ? 0ull : (~0ull << sh));
-              B[col] = A[col] & ballot(wr[r][col] == xr[r]) & cap;
-              any |= B[col];
-            }
-            if (!any) goto found;
-#pragma unroll
-            for (int col = 0; col < WC; ++col) A[col] = B[col];
-            ++L;
-          }
-        }
-      }
-    found:
-      if (L >= job.MIN) {
-        uint32_t d = 0;
-#pragma unroll
-        for (int col = WC - 1; col >= 0; --col) {
-          if (d == 0 && A[col]) d = 64u * col + 64u - (uint32_t)__clzll(A[col]);
-        }
-        val = 1u | (L << 1) | ((d & 0xFFu) << 9);
-        p = h + L;
-      } else {
-        val = h << 1;
-        p = h + 1;
-      }
+      val = h << 1;
+      p = h + 1;
     }
     if (lane == (ntok & 63u)) desc = val;
     ++ntok;
@@ -525,6 +532,221 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
   if (lane == 0) {
     job.sizes[0] = (ntok + 7) / 8;
     job.sizes[1] = pay;
+  }
+}
+
+// ---- the same parse with the chunk split across waves ---------------------
+
+constexpr uint32_t kSpecWaves = 16;      // waves of the split-parse encoder
+constexpr uint32_t kSpecMaxSyms = 4096;  // chunks it takes (16-bit positions)
+
+__host__ __device__ constexpr uint64_t spec_bitmap_words(uint32_t C) { return (C + 31) / 32 + 2; }
+// LDS: [pad | chunk | hit bitmap | token starts | pointer starts | (L, d) per
+// position | prefix counts of both bitmaps | segment ends]
+template <int S, int WC>
+__host__ __device__ constexpr uint64_t spec_lds_bytes(uint32_t C) {
+  return encode_lds(C, S, WC) + 2 * 4 * spec_bitmap_words(C) + align_up(2ull * C, 16) +
+         2 * 4 * (spec_bitmap_words(C) + 1) + 4 * kSpecWaves;
+}
+
+// Sets (or clears) bits [a, b) of an LDS bitmap; all lanes of the wave.
+__device__ __forceinline__ void bits_range(uint32_t* bm, uint32_t a, uint32_t b, bool set) {
+  if (a >= b) return;
+  const uint32_t w0 = a >> 5, w1 = (b - 1) >> 5;
+  for (uint32_t w = w0 + lane_id(); w <= w1; w += 64) {
+    uint32_t m = ~0u;
+    if (w == w0) m &= ~0u << (a & 31u);
+    if (w == w1) m &= ~0u >> (31u - ((b - 1) & 31u));
+    if (set) atomicOr(&bm[w], m);
+    else atomicAnd(&bm[w], ~m);
+  }
+}
+
+// Encodes one chunk like encode_chunk (the same stream), with the greedy
+// parse split across the workgroup's waves for latency: wave w parses its
+// segment [w seg, (w + 1) seg) as if a token started at its first position,
+// recording token starts, pointer starts and (L, d) per pointer. The greedy
+// parse is deterministic, so once the true parse reaches a position where a
+// segment's parse has a token start, the two agree from there on. Wave 0
+// walks each boundary in turn: from where the true parse enters segment w it
+// parses token by token (dropping segment w's starts it covers) until it lands
+// on one of segment w's starts, and continues from that segment's end. Every
+// wave then encodes 64-token groups independently: a token's position comes
+// from prefix counts of the token bitmap, a group's payload offset from the
+// pointers before it.
+template <int S, int WC>
+__device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
+  using T = typename SymType<S>::T;
+  constexpr uint32_t kBlock = Geo<S>::kBlock;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = tid >> 6;
+  const uint32_t nwaves = blockDim.x >> 6;
+  const uint32_t c = job.c;
+  uint8_t* stage = lds + pad_bytes<S, WC>();
+  uint32_t* hits = reinterpret_cast<uint32_t*>(stage + chunk_lds_bytes(job.C, S));
+  const uint32_t nhw = (uint32_t)hit_words(job.C, S);
+  const uint32_t tw = (uint32_t)spec_bitmap_words(job.C);
+  uint32_t* tok = hits + nhw;
+  uint32_t* ptr = tok + tw;
+  uint16_t* tinfo = reinterpret_cast<uint16_t*>(ptr + tw);
+  uint32_t* pc_tok = reinterpret_cast<uint32_t*>(tinfo + align_up(job.C, 8));
+  uint32_t* pc_ptr = pc_tok + tw + 1;
+  uint32_t* ends = pc_ptr + tw + 1;
+
+  stage_chunk<S>(job, stage);
+  for (uint32_t k = tid; k < nhw; k += blockDim.x) hits[k] = 0;
+  for (uint32_t k = tid; k < 2 * tw; k += blockDim.x) tok[k] = 0;
+  __syncthreads();
+  const bool sampled = job.MIN >= 2;
+  {
+    const uint4* w4 = reinterpret_cast<const uint4*>(stage);
+    const uint32_t nblocks = (c + kBlock - 1) / kBlock;
+    for (uint32_t b = wave; b < nblocks; b += nwaves) {
+      const uint32_t base = b * kBlock;
+      if (sampled) {
+        if (base >= job.W) hit_block<S, false, 2>(w4, base, job.W, hits);
+        else hit_block<S, true, 2>(w4, base, job.W, hits);
+      } else {
+        if (base >= job.W) hit_block<S, false, 1>(w4, base, job.W, hits);
+        else hit_block<S, true, 1>(w4, base, job.W, hits);
+      }
+    }
+  }
+  __syncthreads();
+
+  const T* win = reinterpret_cast<const T*>(stage);
+  uint64_t wmask[WC];
+#pragma unroll
+  for (int col = 0; col < WC; ++col) wmask[col] = ballot(64u * col + lane + 1u <= job.W);
+  const uint32_t seg = (c + nwaves - 1) / nwaves;
+
+  // ---- each wave: the greedy parse of its own segment
+  {
+    const uint32_t s0 = min(c, wave * seg), s1 = min(c, s0 + seg);
+    uint32_t p = s0;
+    CandCursor cc;
+    cc.init(hits, nhw, sampled);
+    while (p < s1) {
+      const uint32_t h = cc.next(p, c, hits, nhw, sampled);
+      if (h > p) {  // literals up to the next candidate
+        const uint32_t e = min(h, s1);
+        bits_range(tok, p, e, true);
+        p = e;
+        continue;
+      }
+      const uint32_t key = search_token<S, WC>(win, p, c, job.W, job.MIN, wmask, lane);
+      if (lane == 0) {
+        atomicOr(&tok[p >> 5], 1u << (p & 31u));
+        if (key) {
+          atomicOr(&ptr[p >> 5], 1u << (p & 31u));
+          tinfo[p] = (uint16_t)((key >> 9) << 8 | (key & 0xFFu));
+        }
+      }
+      p += key ? key >> 9 : 1u;
+    }
+    if (lane == 0) ends[wave] = p;
+  }
+  __syncthreads();
+
+  // ---- wave 0: repair each segment boundary
+  if (wave == 0) {
+    uint32_t q = ends[0];
+    CandCursor cc;
+    cc.init(hits, nhw, sampled);
+    for (uint32_t w = 1; w < nwaves; ++w) {
+      const uint32_t s0 = w * seg;
+      if (s0 >= c) break;
+      const uint32_t s1 = min(c, s0 + seg);
+      // segment w's starts before q lie inside tokens of the true parse
+      bits_range(tok, s0, min(q, s1), false);
+      bits_range(ptr, s0, min(q, s1), false);
+      wave_sync();
+      while (q < s1 && !((tok[q >> 5] >> (q & 31u)) & 1u)) {
+        const uint32_t h = cc.next(q, c, hits, nhw, sampled);
+        uint32_t key = 0;
+        if (h == q) key = search_token<S, WC>(win, q, c, job.W, job.MIN, wmask, lane);
+        const uint32_t L = key ? key >> 9 : 1u;
+        if (lane == 0) {
+          atomicOr(&tok[q >> 5], 1u << (q & 31u));
+          if (key) {
+            atomicOr(&ptr[q >> 5], 1u << (q & 31u));
+            tinfo[q] = (uint16_t)((key >> 9) << 8 | (key & 0xFFu));
+          }
+        }
+        wave_sync();
+        bits_range(tok, q + 1, min(q + L, s1), false);
+        bits_range(ptr, q + 1, min(q + L, s1), false);
+        wave_sync();
+        q += L;
+      }
+      if (q < s1) q = ends[w];  // met segment w's parse: it is the true one from here
+    }
+  }
+  __syncthreads();
+
+  // ---- prefix counts of both bitmaps (wave 0), then the groups (all waves)
+  const uint32_t nbw = (c + 31) / 32;
+  if (wave == 0) {
+    uint32_t run_t = 0, run_p = 0;
+    for (uint32_t base = 0; base < nbw; base += 64) {
+      const uint32_t w = base + lane;
+      const uint32_t ct = w < nbw ? (uint32_t)__popc(tok[w]) : 0u;
+      const uint32_t cp = w < nbw ? (uint32_t)__popc(ptr[w]) : 0u;
+      const uint32_t it = wave_incl_scan(ct), ip = wave_incl_scan(cp);
+      if (w < nbw) {
+        pc_tok[w] = run_t + it - ct;
+        pc_ptr[w] = run_p + ip - cp;
+      }
+      run_t += readlane(it, 63);
+      run_p += readlane(ip, 63);
+    }
+    if (lane == 0) {
+      pc_tok[nbw] = run_t;
+      pc_ptr[nbw] = run_p;
+    }
+  }
+  __syncthreads();
+  const uint32_t ntok = pc_tok[nbw], nptr = pc_ptr[nbw];
+  const uint32_t groups = (ntok + 63) / 64;
+  for (uint32_t g = wave; g < groups; g += nwaves) {
+    const uint32_t r = 64 * g + lane;  // this lane's token rank
+    uint32_t p = 0;
+    if (r < ntok) {
+      // the word holding it: the last word whose prefix count is <= r
+      uint32_t lo = 0, hi = nbw - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) / 2;
+        if (pc_tok[mid] <= r) lo = mid;
+        else hi = mid - 1;
+      }
+      uint32_t m = tok[lo], k = r - pc_tok[lo], bit = 0;
+#pragma unroll
+      for (uint32_t width = 16; width >= 1; width >>= 1) {
+        const uint32_t lowc = (uint32_t)__popc(m & ((1u << width) - 1u));
+        if (k >= lowc) {
+          k -= lowc;
+          m >>= width;
+          bit += width;
+        }
+      }
+      p = 32 * lo + bit;
+    }
+    uint32_t desc = p << 1;
+    if (r < ntok && ((ptr[p >> 5] >> (p & 31u)) & 1u)) {
+      const uint32_t ti = tinfo[p];
+      desc = 1u | ((ti >> 8) << 1) | ((ti & 0xFFu) << 9);
+    }
+    // payload before the group: S per literal and 2 per pointer among its
+    // first 64 g tokens
+    const uint32_t p0 = readlane(p, 0);
+    const uint32_t before_ptr = pc_ptr[p0 >> 5] + (uint32_t)__popc(ptr[p0 >> 5] & ((1u << (p0 & 31u)) - 1u));
+    uint32_t pay = S * (64 * g - before_ptr) + 2 * before_ptr;
+    encode_group<S>(min(64u, ntok - 64 * g), desc, g, win, job.slot, job.flag_area, pay);
+  }
+  if (tid == 0) {
+    job.sizes[0] = (ntok + 7) / 8;
+    job.sizes[1] = S * (ntok - nptr) + 2 * nptr;
   }
 }
 

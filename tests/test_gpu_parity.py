@@ -227,3 +227,35 @@ def test_waves_per_chunk_does_not_change_bytes(S):
         assert len(outs) == 1 and outs.pop() == oracle.compress(x, S, 1024, 200, 2)
     finally:
         gpulz.gpulz_set_default_params(S, *saved)
+
+
+def _repetitive(n_sym, S, seed):
+    """Long periodic runs (matches that cross many 1/16-chunk segments), broken
+    by random symbols."""
+    rng = np.random.default_rng(seed)
+    period = rng.integers(1, 40, size=1)[0]
+    base = rng.integers(0, 256, size=(period, S), dtype=np.uint8)
+    x = np.tile(base, (n_sym // period + 1, 1))[:n_sym].copy()
+    noise = rng.random(n_sym) < 0.01
+    x[noise] = rng.integers(0, 256, size=(int(noise.sum()), S), dtype=np.uint8)
+    return x.reshape(-1)
+
+
+# Launches with few chunks split each chunk's parse across 16 waves: segments
+# of a chunk with C < 16 are partly empty, long pointers cross several
+# segments, and chunk counts on either side of the launch rule take the two
+# encoders; all must give the oracle's stream.
+@pytest.mark.parametrize("S,C,n_sym,kind", [
+    (1, 1, 500, "mixed"), (2, 3, 700, "rep"), (4, 15, 1200, "rep"), (8, 16, 800, "mixed"),
+    (1, 17, 5000, "rep"), (2, 100, 20000, "rep"), (2, 4096, 30000, "rep"), (1, 4096, 60000, "mixed"),
+    (2, 64, 1024 * 64, "mixed"), (2, 64, 1025 * 64, "mixed"), (4, 64, 512 * 64, "rep"),
+    (4, 64, 513 * 64, "rep"), (8, 4096, 3 * 4096 + 5, "rep")])
+def test_split_parse_matches_oracle(S, C, n_sym, kind):
+    x = _repetitive(n_sym, S, C + n_sym) if kind == "rep" else synth.mixed(n_sym * S, S, C)
+    for W, MIN in ((256, 2), (37, 1), (64, 3)):
+        _say("split parse", S, C, n_sym, kind, W, MIN)
+        st, s, _, canary = gpu_compress(x, S, C, W, MIN)
+        assert st == gpulz.GPULZ_OK and canary
+        assert s == oracle.compress(x, S, C, W, MIN)
+        st, d, n, canary = gpu_decompress(s, x.size)
+        assert st == gpulz.GPULZ_OK and canary and d == x.tobytes()
