@@ -160,16 +160,35 @@ def run_sweep(args):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
-        d = gpulz.decompress(comp.out[:nbytes])
-        if not torch.equal(d, x):
+        # decompression into preallocated buffers, same stream
+        s_in = comp.out[:nbytes]
+        d = torch.empty(size, dtype=torch.uint8, device="cuda")
+        ws_bytes = gpulz.gpulz_decompress_workspace_size(nbytes)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        meta = torch.zeros(2, dtype=torch.int64, device="cuda")
+
+        def dec():
+            gpulz._check(gpulz.gpulz_decompress(s_in.data_ptr(), nbytes, d.data_ptr(), size,
+                                                meta.data_ptr(), meta.data_ptr() + 8, ws.data_ptr(),
+                                                ws_bytes, stream.cuda_stream), "gpulz_decompress")
+        dec()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            dec()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dms = e0.elapsed_time(e1) / args.steps
+        if int(meta[1]) != 0 or not torch.equal(d, x):
             raise SystemExit(f"round trip mismatch for {kind}")
         print(json.dumps({"metric": "compress GB/s (input) + ratio", "workload": f"sweep-{kind}",
                           "symbol_bytes": S, "input_bytes": size, "value": round(size / ms / 1e6, 3),
                           "unit": "GB/s", "ms_per_step": round(ms, 4),
                           "ratio": round(size / nbytes, 4), "chunk_symbols": C, "window": W,
                           "min_match": MIN, "waves_per_chunk": waves,
+                          "decompress_GBps": round(size / dms / 1e6, 3),
                           "autotune_candidates": len(tuned["measurements"])}), flush=True)
-        del x, comp, d
+        del x, comp, d, ws
         torch.cuda.empty_cache()
 
 
