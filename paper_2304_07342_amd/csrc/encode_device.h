@@ -541,12 +541,13 @@ constexpr uint32_t kSpecWaves = 16;      // waves of the split-parse encoder
 constexpr uint32_t kSpecMaxSyms = 4096;  // chunks it takes (16-bit positions)
 
 __host__ __device__ constexpr uint64_t spec_bitmap_words(uint32_t C) { return (C + 31) / 32 + 2; }
-// LDS: [pad | chunk | hit bitmap | token starts | pointer starts | (L, d) per
-// position | prefix counts of both bitmaps | segment ends]
+// LDS: [pad | chunk | hit bitmap | token starts | pointer starts | the same
+// two for the extensions | (L, d) per position | prefix counts of the token
+// and pointer bitmaps | segment ends | meeting points]
 template <int S, int WC>
 __host__ __device__ constexpr uint64_t spec_lds_bytes(uint32_t C) {
-  return encode_lds(C, S, WC) + 2 * 4 * spec_bitmap_words(C) + align_up(2ull * C, 16) +
-         2 * 4 * (spec_bitmap_words(C) + 1) + 4 * kSpecWaves;
+  return encode_lds(C, S, WC) + 4 * 4 * spec_bitmap_words(C) + align_up(2ull * C, 16) +
+         2 * 4 * (spec_bitmap_words(C) + 1) + 2 * 4 * kSpecWaves;
 }
 
 // Sets (or clears) bits [a, b) of an LDS bitmap; all lanes of the wave.
@@ -567,12 +568,13 @@ __device__ __forceinline__ void bits_range(uint32_t* bm, uint32_t a, uint32_t b,
 // segment [w seg, (w + 1) seg) as if a token started at its first position,
 // recording token starts, pointer starts and (L, d) per pointer. The greedy
 // parse is deterministic, so once the true parse reaches a position where a
-// segment's parse has a token start, the two agree from there on. Wave 0
-// walks each boundary in turn: from where the true parse enters segment w it
-// parses token by token (dropping segment w's starts it covers) until it lands
-// on one of segment w's starts, and continues from that segment's end. Every
-// wave then encodes 64-token groups independently: a token's position comes
-// from prefix counts of the token bitmap, a group's payload offset from the
+// segment's parse has a token start, the two agree from there on. Each wave
+// then extends its parse into the next segment until it lands on one of that
+// segment's starts, and wave 0 joins the segments: where the true parse leaves
+// a segment at that segment's own end, the extension is spliced in; otherwise
+// wave 0 walks the boundary token by token until the parses meet. Every wave
+// then encodes 64-token groups independently: a token's position comes from
+// prefix counts of the token bitmap, a group's payload offset from the
 // pointers before it.
 template <int S, int WC>
 __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
@@ -589,14 +591,17 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
   const uint32_t tw = (uint32_t)spec_bitmap_words(job.C);
   uint32_t* tok = hits + nhw;
   uint32_t* ptr = tok + tw;
-  uint16_t* tinfo = reinterpret_cast<uint16_t*>(ptr + tw);
+  uint32_t* xtok = ptr + tw;  // extension parses
+  uint32_t* xptr = xtok + tw;
+  uint16_t* tinfo = reinterpret_cast<uint16_t*>(xptr + tw);
   uint32_t* pc_tok = reinterpret_cast<uint32_t*>(tinfo + align_up(job.C, 8));
   uint32_t* pc_ptr = pc_tok + tw + 1;
   uint32_t* ends = pc_ptr + tw + 1;
+  uint32_t* meet = ends + kSpecWaves;
 
   stage_chunk<S>(job, stage);
   for (uint32_t k = tid; k < nhw; k += blockDim.x) hits[k] = 0;
-  for (uint32_t k = tid; k < 2 * tw; k += blockDim.x) tok[k] = 0;
+  for (uint32_t k = tid; k < 4 * tw; k += blockDim.x) tok[k] = 0;
   __syncthreads();
   const bool sampled = job.MIN >= 2;
   {
@@ -649,7 +654,36 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
   }
   __syncthreads();
 
-  // ---- wave 0: repair each segment boundary
+  // ---- each wave: extend its parse into the next segment until it lands on
+  // a start of that segment's own parse (recorded in the extension bitmaps;
+  // the (L, d) of a position does not depend on which parse reached it)
+  if (wave + 1 < nwaves && (wave + 1) * seg < c) {
+    const uint32_t n0 = (wave + 1) * seg, n1 = min(c, n0 + seg);
+    uint32_t q = ends[wave];
+    CandCursor cc;
+    cc.init(hits, nhw, sampled);
+    while (q < n1 && !((tok[q >> 5] >> (q & 31u)) & 1u)) {
+      const uint32_t h = cc.next(q, c, hits, nhw, sampled);
+      uint32_t key = 0;
+      if (h == q) key = search_token<S, WC>(win, q, c, job.W, job.MIN, wmask, lane);
+      if (lane == 0) {
+        atomicOr(&xtok[q >> 5], 1u << (q & 31u));
+        if (key) {
+          atomicOr(&xptr[q >> 5], 1u << (q & 31u));
+          tinfo[q] = (uint16_t)((key >> 9) << 8 | (key & 0xFFu));
+        }
+      }
+      q += key ? key >> 9 : 1u;
+    }
+    if (lane == 0) meet[wave] = q;
+  }
+  __syncthreads();
+
+  // ---- wave 0: join the segments. Where the true parse leaves segment w - 1
+  // at that segment's own end, wave w - 1's extension is its continuation:
+  // splice it in over [w seg, meeting point). Otherwise walk the boundary
+  // token by token (dropping segment w's starts it covers) until it lands on
+  // one of segment w's starts.
   if (wave == 0) {
     uint32_t q = ends[0];
     CandCursor cc;
@@ -658,6 +692,22 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
       const uint32_t s0 = w * seg;
       if (s0 >= c) break;
       const uint32_t s1 = min(c, s0 + seg);
+      if (q == ends[w - 1]) {
+        const uint32_t m = meet[w - 1], e = min(m, s1);
+        if (s0 < e) {
+          const uint32_t w0 = s0 >> 5, w1 = (e - 1) >> 5;
+          for (uint32_t k = w0 + lane; k <= w1; k += 64) {
+            uint32_t msk = ~0u;
+            if (k == w0) msk &= ~0u << (s0 & 31u);
+            if (k == w1) msk &= ~0u >> (31u - ((e - 1) & 31u));
+            tok[k] = (tok[k] & ~msk) | (xtok[k] & msk);
+            ptr[k] = (ptr[k] & ~msk) | (xptr[k] & msk);
+          }
+        }
+        wave_sync();
+        q = m < s1 ? ends[w] : m;
+        continue;
+      }
       // segment w's starts before q lie inside tokens of the true parse
       bits_range(tok, s0, min(q, s1), false);
       bits_range(ptr, s0, min(q, s1), false);
