@@ -197,7 +197,7 @@ def run_small(args):
     single launches and of graph replays of the same call."""
     import torch
     from paper_2304_07342_amd import gpulz, synth
-    cfg = synth.CONFIGS[0]
+    cfg = synth.WORKLOADS[synth.CODES_1MIB]
     S, C, W, MIN = cfg["S"], cfg["C"], cfg["W"], cfg["MIN"]
     x = torch.from_numpy(cfg["make"]().view(np.uint8).reshape(-1)).to("cuda")
     n = x.numel()
@@ -252,8 +252,8 @@ def run_scan(args):
     ratio of each."""
     import torch
     from paper_2304_07342_amd import gpulz, synth
-    for key in (1, 0):
-        cfg = synth.CONFIGS[key]
+    for key in (synth.FIELD_256MIB, synth.CODES_1MIB):
+        cfg = synth.WORKLOADS[key]
         S, C, W, MIN = cfg["S"], cfg["C"], cfg["W"], cfg["MIN"]
         x = torch.from_numpy(cfg["make"]().view(np.uint8).reshape(-1)).to("cuda")
         n = x.numel()
@@ -343,7 +343,7 @@ def run_host(args):
     them."""
     import torch
     from paper_2304_07342_amd import gpulz, stream_host, synth
-    cfg = synth.CONFIGS[1]
+    cfg = synth.WORKLOADS[synth.FIELD_256MIB]
     S, C, W, MIN = cfg["S"], cfg["C"], cfg["W"], cfg["MIN"]
     x = np.tile(cfg["make"]().view(np.uint8).reshape(-1), 4)
     n = x.size
@@ -599,7 +599,7 @@ def main():
                          "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only; multi-GPU runs are not part of this build",
+        print("bench.py measures one GPU only; multi-GPU runs are not supported",
               file=sys.stderr)
         sys.exit(2)
 
@@ -624,7 +624,7 @@ def main():
     import torch
     from paper_2304_07342_amd import gpulz, synth
 
-    cfg = synth.CONFIGS[1]
+    cfg = synth.WORKLOADS[synth.FIELD_256MIB]
     S, C, W, MIN = cfg["S"], cfg["C"], cfg["W"], cfg["MIN"]
     print(f"[bench] generating {cfg['name']}", file=sys.stderr, flush=True)
     x = cfg["make"]().view(np.uint8).reshape(-1)

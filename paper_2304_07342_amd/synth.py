@@ -190,14 +190,14 @@ def mixed(nbytes: int, S: int, seed: int) -> np.ndarray:
     return np.concatenate(parts)[:nbytes] if parts else np.zeros(0, dtype=np.uint8)
 
 
-# ---- the benchmark configurations -----------------------------------------
+# ---- the two single-buffer benchmark workloads ------------------------------
 
-def config0() -> np.ndarray:
+def codes_1mib() -> np.ndarray:
     """1 MiB of uint16 Laplace codes with 30% copied runs, seed 0."""
     return laplace_codes(1 << 19, seed=0)
 
 
-def config1() -> np.ndarray:
+def field_256mib() -> np.ndarray:
     """256 MiB float32 field 512 x 512 x 256, seed 1."""
     return sinusoid_field((512, 512, 256), seed=1, dtype=np.float32)
 
@@ -241,7 +241,10 @@ def batch_spec(nbufs: int, seed: int, lo: int = 4 << 10, hi: int = 64 << 20,
     return out
 
 
-CONFIGS = {
-    0: dict(name="laplace-u16-1MiB", S=2, C=2048, W=128, MIN=2, make=config0),
-    1: dict(name="field-f32-256MiB", S=4, C=4096, W=256, MIN=2, make=config1),
+# The two single-buffer workloads by name: 1 MiB of uint16 codes (small
+# enough for the oracle in seconds) and the 256 MiB float32 field.
+WORKLOADS = {
+    "laplace-u16-1MiB": dict(name="laplace-u16-1MiB", S=2, C=2048, W=128, MIN=2, make=codes_1mib),
+    "field-f32-256MiB": dict(name="field-f32-256MiB", S=4, C=4096, W=256, MIN=2, make=field_256mib),
 }
+CODES_1MIB, FIELD_256MIB = "laplace-u16-1MiB", "field-f32-256MiB"

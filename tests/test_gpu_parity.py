@@ -81,10 +81,10 @@ def test_largest_chunk(S):
     assert st == gpulz.GPULZ_OK and d == x.tobytes()
 
 
-def test_config0_full():
-    cfg = synth.CONFIGS[0]
+def test_codes_1mib_full():
+    cfg = synth.WORKLOADS[synth.CODES_1MIB]
     x = cfg["make"]()
-    _say("config0")
+    _say("codes 1 MiB")
     st, s, _, _ = gpu_compress(x, cfg["S"], cfg["C"], cfg["W"], cfg["MIN"])
     assert st == gpulz.GPULZ_OK
     assert s == oracle.compress(x, cfg["S"], cfg["C"], cfg["W"], cfg["MIN"])
@@ -92,16 +92,16 @@ def test_config0_full():
     assert st == gpulz.GPULZ_OK and d == x.tobytes()
 
 
-def test_config1_full_size_sampled_chunks():
+def test_field_256mib_sampled_chunks():
     """256 MiB float32 field at full size with the benchmark's parameters.
     Chunks are independent, so each sampled chunk's table entry and record
     are checked against the oracle run on that chunk alone; the header,
     table sums and an exact GPU round trip cover the rest."""
     import torch
-    cfg = synth.CONFIGS[1]
+    cfg = synth.WORKLOADS[synth.FIELD_256MIB]
     S, C, W, MIN = cfg["S"], cfg["C"], cfg["W"], cfg["MIN"]
     x = cfg["make"]().view(np.uint8).reshape(-1)
-    _say("config1 full size")
+    _say("field 256 MiB")
     c = gpulz.Compressor(x.size, S, C, W, MIN)
     d_in = torch.from_numpy(x).cuda()
     c.compress_async(d_in)

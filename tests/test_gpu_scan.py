@@ -52,7 +52,7 @@ def test_random_cases_match_the_oracle(seed):
 
 
 def test_small_codes_in_full():
-    cfg = synth.CONFIGS[0]
+    cfg = synth.WORKLOADS[synth.CODES_1MIB]
     x = cfg["make"]().view(np.uint8).reshape(-1)
     _say("scan codes 1 MiB")
     ref = oracle.compress(x, cfg["S"], cfg["C"], cfg["W"], cfg["MIN"], policy=1, threads=8)
@@ -62,7 +62,7 @@ def test_small_codes_in_full():
 
 def test_field_full_size_sampled_chunks():
     import torch
-    cfg = synth.CONFIGS[1]
+    cfg = synth.WORKLOADS[synth.FIELD_256MIB]
     S, C, W, MIN = cfg["S"], cfg["C"], cfg["W"], cfg["MIN"]
     x = cfg["make"]().view(np.uint8).reshape(-1)
     _say("scan field full size")
