@@ -286,9 +286,10 @@ __device__ inline uint32_t waves_excl(uint32_t v, uint32_t* scratch, uint32_t& t
 // in_end: end of the stream (no byte at or past it is read); dst: its first
 // output byte.
 //
-// Token i (of the 8 F the flags describe) is handled by wave i / 1024 in
-// round (i / 64) % 16 on lane i % 64, so neighbouring lanes touch
-// neighbouring LDS bytes. Payload offsets come from the literal / pointer
+// Token i (of the 8 F the flags describe) is handled by wave i / (64 R) in
+// round (i / 64) % R on lane i % 64, R = ceil(8 F / 256) rounds per wave, so
+// neighbouring lanes touch neighbouring LDS bytes and small chunks still
+// spread over all four waves. Payload offsets come from the literal / pointer
 // counts (mbcnt within a round, running totals across rounds, one exchange
 // across waves); output positions likewise from the token lengths.
 template <int S>
@@ -315,19 +316,27 @@ __device__ bool decode_chunk_block(const uint8_t* rec, const uint8_t* in_end, ui
   const uint8_t* fl = sm.rec + a;
   const uint8_t* pay = fl + F;
   const uint32_t nt = 8 * F;
-  const uint32_t t0 = 1024 * wave + lane;
+  // R rounds of 64 tokens per wave (R <= 16), so that small chunks spread over
+  // all four waves too
+  const uint32_t R = nt <= 256 ? 1u : (nt + 255) / 256;
+  const uint32_t tpw = 64 * R;
+  const uint32_t t0 = tpw * wave + lane;
 
   // token i's kind: pointer flag bit (only for i < 8 F)
   auto is_ptr = [&](uint32_t i) { return i < nt && ((fl[i >> 3] >> (i & 7)) & 1u); };
-  // the wave's literal / pointer counts: its 1024 tokens are 128 flag bytes,
-  // two per lane
+  // the wave's literal / pointer counts: lane l counts the wave's tokens
+  // R l .. R l + R - 1 (R flag bits at any bit offset, at most 3 bytes)
   uint32_t np, nh;
   {
-    const uint32_t i = 1024 * wave + 16 * lane;  // first of this lane's 16 tokens
+    const uint32_t i = tpw * wave + R * lane;  // first of this lane's R tokens
+    const uint32_t b0 = i >> 3;
     uint32_t fb = 0;
-    if (i < nt) fb = fl[i >> 3];
-    if (i + 8 < nt) fb |= (uint32_t)fl[(i >> 3) + 1] << 8;
-    const uint32_t hmask = i >= nt ? 0u : (nt - i >= 16 ? 0xFFFFu : (1u << (nt - i)) - 1u);
+    if (b0 < F) fb = fl[b0];
+    if (b0 + 1 < F) fb |= (uint32_t)fl[b0 + 1] << 8;
+    if (b0 + 2 < F) fb |= (uint32_t)fl[b0 + 2] << 16;
+    fb >>= (i & 7u);
+    const uint32_t cnt = i >= nt ? 0u : min(R, nt - i);
+    const uint32_t hmask = (1u << cnt) - 1u;
     np = readlane(wave_incl_scan((uint32_t)__popc(fb & hmask)), 63);
     nh = readlane(wave_incl_scan((uint32_t)__popc(hmask)), 63);
   }
@@ -346,7 +355,7 @@ __device__ bool decode_chunk_block(const uint8_t* rec, const uint8_t* in_end, ui
   uint32_t wlen = nh;
   {
     uint32_t lit = lit0, ptr = ptr0;
-    for (int j = 0; j < 16; ++j) {
+    for (uint32_t j = 0; j < R; ++j) {
       const uint32_t i = t0 + 64 * j;
       const bool isp = is_ptr(i);
       const uint64_t pmj = ballot(isp), lm = ballot(i < nt && !isp);
@@ -367,7 +376,7 @@ __device__ bool decode_chunk_block(const uint8_t* rec, const uint8_t* in_end, ui
   uint32_t taken = 0, uend = 0;
   {
     uint32_t lit = lit0, ptr = ptr0, run = wpos0;
-    for (int j = 0; j < 16; ++j) {
+    for (uint32_t j = 0; j < R; ++j) {
       const uint32_t i = t0 + 64 * j;
       const bool has = i < nt;
       const bool isp = is_ptr(i);
@@ -407,7 +416,7 @@ __device__ bool decode_chunk_block(const uint8_t* rec, const uint8_t* in_end, ui
         }
       }
       const uint64_t tb = ballot(tk && isp);
-      if (lane == 0 && !jump) sm.ptrbits[16 * wave + j] = tb;
+      if (lane == 0 && !jump) sm.ptrbits[R * wave + j] = tb;
       lit += popc64(lm);
       ptr += popc64(pmj);
     }
