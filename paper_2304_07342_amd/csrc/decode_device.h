@@ -82,34 +82,44 @@ __device__ inline void parse_header(const uint8_t* h, uint64_t in_bytes, DecodeP
 // blockDim that is a multiple of 64. `scratch` holds blockDim/64 + 1 u64.
 __device__ inline uint64_t scan_table_groups(const uint8_t* in, uint64_t N, uint64_t* group_off,
                                              uint64_t* scratch) {
+  // each thread sums 16 consecutive entries (eight 16-byte loads; the table
+  // starts 16-byte aligned), so 4 threads cover a group of 64; one block-wide
+  // scan per tile of 16 blockDim entries gives every group's offset
+  constexpr uint32_t kPer = 16;
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
   const uint32_t nw = blockDim.x >> 6;
   const uint64_t ngroups = (N + kGroup - 1) / kGroup;
   const uint8_t* table = in + kHeaderBytes;
+  const uint4* t4 = reinterpret_cast<const uint4*>(table);
+  const uint64_t tile = (uint64_t)blockDim.x * kPer;
   uint64_t carry = kHeaderBytes + 8 * N;
-  // each wave sums one group of 64 entries; then the block scans nw groups
-  for (uint64_t g0 = 0; g0 < ngroups; g0 += nw) {
-    const uint64_t g = g0 + wid;
-    uint64_t sum = 0;
-    if (g < ngroups) {
-      const uint64_t i = g * kGroup + lane;
-      uint64_t v = 0;
-      if (i < N) {
-        const uint32_t* e = reinterpret_cast<const uint32_t*>(table + 8 * i);
-        v = (uint64_t)e[0] + e[1];
+  for (uint64_t base = 0; base < N; base += tile) {
+    const uint64_t i0 = base + (uint64_t)tid * kPer;
+    uint64_t v = 0;
+    if (i0 + kPer <= N) {
+#pragma unroll
+      for (uint32_t q = 0; q < kPer / 2; ++q) {
+        const uint4 e = t4[i0 / 2 + q];
+        v += (uint64_t)e.x + e.y + (uint64_t)e.z + e.w;
       }
-      sum = wave_incl_scan_u64(v);  // lane 63 holds the group's sum
+    } else {
+      for (uint32_t k = 0; k < kPer && i0 + k < N; ++k) {
+        const uint32_t* e = reinterpret_cast<const uint32_t*>(table + 8 * (i0 + k));
+        v += (uint64_t)e[0] + e[1];
+      }
     }
-    if (lane == 63) scratch[wid] = sum;
+    const uint64_t incl = wave_incl_scan_u64(v);
+    if (lane == 63) scratch[wid] = incl;
     __syncthreads();
-    if (wid == 0) {
-      const uint64_t w = lane < nw ? scratch[lane] : 0;
-      const uint64_t wi = wave_incl_scan_u64(w);
-      if (lane < nw && g0 + lane < ngroups) group_off[g0 + lane] = carry + wi - w;
-      if (lane == nw - 1) scratch[nw] = wi;
+    uint64_t before = 0, total = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+      const uint64_t x = scratch[w];
+      before += w < wid ? x : 0ull;
+      total += x;
     }
-    __syncthreads();
-    carry += scratch[nw];
+    // i0 is a multiple of 64 exactly on every fourth thread
+    if ((tid & 3u) == 0 && i0 < N) group_off[i0 / kGroup] = carry + before + incl - v;
+    carry += total;
     __syncthreads();
   }
   if (tid == 0) group_off[ngroups] = carry;
