@@ -57,7 +57,19 @@ __global__ __launch_bounds__(256) void hist_kernel(EncArgs a) {
     const uint64_t w0 = (uint64_t)blockIdx.x * per;
     const uint64_t w1 = w0 + per < words ? w0 + per : words;
     const uint4* in4 = reinterpret_cast<const uint4*>(a.in);
-    for (uint64_t w = w0 + tid; w < w1; w += 256) {
+    const uint64_t wfull = n / 16;  // whole 16-byte words
+    uint64_t w = w0 + tid;
+    // four loads in flight per thread, then their 64 bytes counted
+    for (; w + 3 * 256 < w1 && w + 3 * 256 < wfull; w += 4 * 256) {
+      uint4 q[4];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) q[u] = in4[w + u * 256];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u)
+#pragma unroll
+        for (uint32_t b = 0; b < 16; ++b) atomicAdd(&mine[byte_of(q[u], b)], 1u);
+    }
+    for (; w < w1; w += 256) {
       if (16 * w + 16 <= n) {
         const uint4 q = in4[w];
 #pragma unroll
@@ -491,42 +503,85 @@ __global__ __launch_bounds__(1024) void dec_prepare_kernel(DecArgs a) {
     }
     return;
   }
-  for (uint32_t k = tid; k < (1u << kLutBits); k += 1024) T.lut[k] = 0;
-  for (uint32_t k = tid; k < kMaxSubtables * 16; k += 1024) T.lut2[k] = 0;
-  __syncthreads();
   if (tid < 256 && sm.len[tid]) {
     const uint32_t l = sm.len[tid];
     uint32_t r = 0;
     for (uint32_t t = 0; t < tid; ++t) r += sm.len[t] == l;
     T.by_rank[T.rank0[l] + r] = (uint8_t)tid;
-    const uint32_t code = T.first[l] + r;
-    if (l <= kLutBits) {
-      const uint32_t base = code << (kLutBits - l);
-      for (uint32_t k = 0; k < (1u << (kLutBits - l)); ++k) T.lut[base + k] = (uint16_t)(l << 8 | tid);
-    } else {
-      // long codes follow every shorter one, so their 11-bit prefixes run
-      // consecutively from first[12] / 2 (the start of length 12, left-justified)
-      const uint32_t p0 = T.first[kLutBits + 1] >> 1;
-      const uint32_t base = code << (kLimit - l);  // 15-bit left-justified
-      for (uint32_t k = 0; k < (1u << (kLimit - l)); ++k) {
-        const uint32_t v = base + k, t = (v >> 4) - p0;
-        if (t < kMaxSubtables) {
-          T.lut[v >> 4] = (uint16_t)(0x8000u | t);
-          T.lut2[t * 16 + (v & 15u)] = (uint16_t)(l << 8 | tid);
-        } else {
-          sm.bad = 1;
+  }
+  __syncthreads();
+  // two-level table, every entry decoded on its own thread: an 11-bit prefix
+  // holds the code of length <= 11 it starts with; prefixes from first(12) / 2
+  // on (where the codes longer than 11 bits begin, being the last codes) point
+  // to 16-entry subtables over the next 4 bits; anything else matches no code
+  const uint32_t p0 = T.first[kLutBits + 1] >> 1;
+  for (uint32_t k = tid; k < (1u << kLutBits); k += 1024) {
+    uint32_t e = 0;
+    for (uint32_t l = 1; l <= kLutBits; ++l) {
+      const uint32_t d = (k >> (kLutBits - l)) - T.first[l];
+      if (d < T.count[l]) {
+        e = l << 8 | T.by_rank[T.rank0[l] + d];
+        break;
+      }
+    }
+    if (e == 0 && k >= p0 && k - p0 < kMaxSubtables) e = 0x8000u | (k - p0);
+    T.lut[k] = (uint16_t)e;
+  }
+  for (uint32_t k = tid; k < kMaxSubtables * 16; k += 1024) {
+    const uint32_t prefix = p0 + k / 16;
+    uint32_t e = 0;
+    if (prefix < (1u << kLutBits)) {
+      const uint32_t v = prefix << 4 | (k & 15u);  // 15-bit window
+      for (uint32_t l = kLutBits + 1; l <= kLimit; ++l) {
+        const uint32_t d = (v >> (kLimit - l)) - T.first[l];
+        if (d < T.count[l]) {
+          e = l << 8 | T.by_rank[T.rank0[l] + d];
+          break;
         }
       }
     }
+    T.lut2[k] = (uint16_t)e;
   }
-  // record sizes from the table of code bits
+  // record sizes from the table of code bits: 8 entries per thread per
+  // tile, read with 16-byte loads before any size is written (the table
+  // starts 16-byte aligned; sizes is 256-byte aligned)
   const uint32_t* bits_tab = reinterpret_cast<const uint32_t*>(a.in + kPre);
-  for (uint64_t i = tid; i < T.N; i += 1024) {
-    const uint32_t c = (uint32_t)(T.n - i * kChunk < kChunk ? T.n - i * kChunk : kChunk);
-    const uint32_t bits = bits_tab[i];
-    if (bits > kLimit * c) sm.bad = 1;
-    a.sizes[2 * i] = offsets_bytes((c + kSub - 1) / kSub);
-    a.sizes[2 * i + 1] = 4 * ((bits + 31) / 32);
+  for (uint64_t base = 0; base < T.N; base += 8 * 1024) {
+    const uint64_t i0 = base + 8 * (uint64_t)tid;
+    if (i0 >= T.N) continue;
+    uint32_t bits[8];
+    if (i0 + 8 <= T.N) {
+      const uint4 lo = reinterpret_cast<const uint4*>(bits_tab + i0)[0];
+      const uint4 hi = reinterpret_cast<const uint4*>(bits_tab + i0)[1];
+      bits[0] = lo.x, bits[1] = lo.y, bits[2] = lo.z, bits[3] = lo.w;
+      bits[4] = hi.x, bits[5] = hi.y, bits[6] = hi.z, bits[7] = hi.w;
+    } else {
+#pragma unroll
+      for (uint32_t k = 0; k < 8; ++k) bits[k] = i0 + k < T.N ? bits_tab[i0 + k] : 0u;
+    }
+    uint32_t sz[16];
+    bool bad = false;
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) {
+      const uint64_t i = i0 + k;
+      const uint32_t c = i < T.N ? (uint32_t)(T.n - i * kChunk < kChunk ? T.n - i * kChunk : kChunk) : 0u;
+      bad = bad || bits[k] > kLimit * c;
+      sz[2 * k] = i < T.N ? offsets_bytes((c + kSub - 1) / kSub) : 0u;
+      sz[2 * k + 1] = 4 * ((bits[k] + 31) / 32);
+    }
+    if (bad) sm.bad = 1;
+    if (i0 + 8 <= T.N) {
+      uint4* dst = reinterpret_cast<uint4*>(a.sizes + 2 * i0);
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) dst[q] = make_uint4(sz[4 * q], sz[4 * q + 1], sz[4 * q + 2], sz[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (uint32_t k = 0; k < 8; ++k)
+        if (i0 + k < T.N) {
+          a.sizes[2 * (i0 + k)] = sz[2 * k];
+          a.sizes[2 * (i0 + k) + 1] = sz[2 * k + 1];
+        }
+    }
   }
   __syncthreads();
   const uint64_t sum = stream::scan_record_sizes<16>(a.sizes, T.N, a.offs, sm.scratch);
