@@ -113,66 +113,82 @@ __device__ __forceinline__ typename SymType<4 * S>::T load4_sub(const void* p) {
   }
 }
 
-// Number of leading equal symbols (0..4) of the 4-symbol runs at a and b
-// (LDS, any symbol alignment).
+// 4 S bytes (S = 1 or 2) of LDS starting sh bytes (0..3) past the dword at
+// p, read as aligned dwords (wide LDS reads below dword alignment are slow)
+// and funnel-shifted.
 template <int S>
-__device__ __forceinline__ uint32_t lead_equal4(const typename SymType<S>::T* a,
-                                                const typename SymType<S>::T* b) {
-  if constexpr (S <= 2) {
-    using U = typename SymType<4 * S>::T;
-    const U x = load4_sub<S>(a), y = load4_sub<S>(b);
-    const U t = x ^ y;
-    if constexpr (S == 1) return t ? (uint32_t)__builtin_ctz(t) >> 3 : 4u;
-    else return t ? (uint32_t)__builtin_ctzll(t) >> 4 : 4u;
+__device__ __forceinline__ typename SymType<4 * S>::T load_run(const uint32_t* p, uint32_t sh) {
+  const uint32_t w0 = p[0], w1 = p[1];
+  const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, sh);
+  if constexpr (S == 1) {
+    return lo;
   } else {
-    using T = typename SymType<S>::T;
-    T x[4], y[4];
-    __builtin_memcpy(x, a, 4 * S);
-    __builtin_memcpy(y, b, 4 * S);
-    return x[0] != y[0] ? 0u : x[1] != y[1] ? 1u : x[2] != y[2] ? 2u : x[3] != y[3] ? 3u : 4u;
+    return (uint64_t)lo | ((uint64_t)__builtin_amdgcn_alignbyte(p[2], w1, sh) << 32);
   }
 }
 
 // Exact longest match at chunk position h (h >= 1) over offsets
 // d <= min(W, h), lanes holding offsets (column col, lane l: d = 64 col + l
-// + 1). Each lane extends its own match four look-ahead symbols per LDS read
-// and stops at a mismatch or once its length reaches d (a match never
-// exceeds its offset). The wave maximum of (min(length, d, lim) << 9 | d)
-// is the longest length and, among equal lengths, the largest offset.
-// Returns that key (length = key >> 9, offset = key & 511).
+// + 1). Every step compares the next four symbols of each live offset with
+// those at h as one equality; an offset stays live while all four agree and
+// its length, now at least L0 + 4, is still below d (a match never exceeds
+// its offset). The offsets live at the start of the last step hold the
+// answer: any offset that left earlier is shorter, or was capped at its own
+// d, which is no longer than the length every last-step offset reaches and
+// smaller than their offsets. Their exact lengths come from that step's
+// data: L0 plus the leading equal symbols. The wave maximum of
+// (min(length, d, lim) << 9 | d) is the longest length and, among equal
+// lengths, the largest offset. Returns that key (length = key >> 9,
+// offset = key & 511).
 template <int S, int WC>
 __device__ __forceinline__ uint32_t match_key(const typename SymType<S>::T* win, uint32_t h,
                                               uint32_t lim, uint32_t W, uint32_t lane) {
-  uint32_t len[WC];
-  bool alive[WC];
+  using U = typename SymType<4 * S>::T;
+  const uint8_t* wb = reinterpret_cast<const uint8_t*>(win);
+  // Byte offset of this lane's run in the last column at step 0. Columns are
+  // 64 S bytes apart and steps 4 S bytes, so one dword alignment serves all.
+  // Positions down to h - 64 WC lie in the LDS pad before the chunk; reads
+  // reach at most 4 S + 3 bytes past position h + L0 (L0 < lim <= c - h),
+  // inside the slack after it.
+  const int yb = ((int)h - (int)lane - 1 - 64 * (WC - 1)) * S;
+  const uint32_t ysh = (uint32_t)yb & 3u;
+  const uint32_t* yp = reinterpret_cast<const uint32_t*>(wb + (yb - (int)ysh));
+  const uint32_t xb = h * S;
+  const uint32_t xsh = xb & 3u;
+  const uint32_t* xp = reinterpret_cast<const uint32_t*>(wb + (xb - xsh));
+  // live offsets as wave masks, one per column
+  uint64_t live[WC], start[WC];
+  U yv[WC];
 #pragma unroll
   for (int col = 0; col < WC; ++col) {
     const uint32_t d = 64u * col + lane + 1u;
-    alive[col] = (d <= W) & (d <= h);
-    len[col] = 0;
+    live[col] = ballot((d <= W) & (d <= h));
   }
-  for (uint32_t L0 = 0; L0 < lim; L0 += 4) {
-    // positions h + L0 - d + 3 >= -64 WC lie in the LDS pad before the
-    // chunk, h + L0 + 3 <= c + 2 in the slack after it
-    const typename SymType<S>::T* x = win + h + L0;
+  U xv;
+  uint32_t L0 = 0;
+  while (true) {
+    xv = load_run<S>(xp + S * (L0 / 4), xsh);
+    const uint32_t n0 = L0 + 4;
     uint64_t any = 0;
 #pragma unroll
     for (int col = 0; col < WC; ++col) {
-      const uint32_t d = 64u * col + lane + 1u;
-      const uint32_t r = lead_equal4<S>(x, x - d);
-      len[col] += alive[col] ? r : 0u;
-      alive[col] = alive[col] & (r == 4u) & (len[col] < d);
-      any |= ballot(alive[col]);
+      yv[col] = load_run<S>(yp + S * (L0 / 4) + 16 * S * (WC - 1 - col), ysh);
+      start[col] = live[col];
+      // offsets d <= L0 + 4 end here
+      live[col] &= ballot(yv[col] == xv) & ballot(64u * col + lane + 1u > n0);
+      any |= live[col];
     }
-    if (any == 0) break;
+    if (any == 0 || n0 >= lim) break;
+    L0 = n0;
   }
   uint32_t key = 0;
 #pragma unroll
   for (int col = 0; col < WC; ++col) {
     const uint32_t d = 64u * col + lane + 1u;
-    const uint32_t Lc = min(min(len[col], d), lim);
-    const uint32_t k = (d <= W) & (d <= h) ? (Lc << 9) | d : 0u;
-    key = max(key, k);
+    // leading equal symbols of the last step (4 when all agree)
+    const uint32_t r = (uint32_t)__builtin_ctzg(xv ^ yv[col], 32 * S) / (8u * S);
+    const uint32_t Lc = min(min(L0 + r, d), lim);
+    key = max(key, __builtin_amdgcn_inverse_ballot_w64(start[col]) ? (Lc << 9) | d : 0u);
   }
   return wave_max_u32(key);
 }
