@@ -352,6 +352,29 @@ __device__ bool decode_chunk_block(const uint8_t* rec, const uint8_t* in_end, ui
   }
   uint32_t tot;
   const uint32_t x1 = waves_excl((nh - np) | (np << 16), sm.scratch, tot);
+  if ((tot >> 16) == 0) {
+    // no pointer: the record is valid exactly when its tokens are the chunk's
+    // c literals (F = ceil(c / 8) flag bytes, P = c S payload bytes), and then
+    // the payload is the chunk. It is copied out of LDS with one funnel shift
+    // (its start's offset within a dword is the same for every word).
+    if (F != (c + 7) / 8 || P != c * S) return false;
+    const uint32_t nb = c * S, base = a + F, sh = base & 3u;
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(sm.rec + (base - sh));
+    if (((uintptr_t)dst & 15u) == 0) {
+      for (uint32_t k = tid; k < nb / 16; k += kDecThreads) {
+        const uint32_t* q = w + 4 * k;
+        const uint32_t q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+        const uint32_t q4 = sh ? q[4] : 0u;  // read only when it holds payload bytes
+        *reinterpret_cast<uint4*>(dst + 16 * k) =
+            make_uint4(__builtin_amdgcn_alignbyte(q1, q0, sh), __builtin_amdgcn_alignbyte(q2, q1, sh),
+                       __builtin_amdgcn_alignbyte(q3, q2, sh), __builtin_amdgcn_alignbyte(q4, q3, sh));
+      }
+      for (uint32_t b = (nb & ~15u) + tid; b < nb; b += kDecThreads) dst[b] = sm.rec[base + b];
+    } else {
+      for (uint32_t b = tid; b < nb; b += kDecThreads) dst[b] = sm.rec[base + b];
+    }
+    return true;
+  }
   const uint32_t lit0 = x1 & 0xFFFFu, ptr0 = x1 >> 16;
   // Pointer symbols are resolved in parallel (pointer jumping, below) when the
   // chunk has many pointers and its decoded bytes leave room in `out` for a

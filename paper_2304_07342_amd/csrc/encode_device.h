@@ -42,9 +42,10 @@ namespace enc {
 
 constexpr int kEncodeWaves = 4;
 
-// Match search at a hit: per-lane run lengths (match_key) or per-row offset
-// masks. Measured on MI355X: run lengths are 22% faster on dense 2-byte
-// codes, row masks 4% faster on the literal-heavy 4-byte field.
+// Match search at a hit: 4-symbol equality steps over offset masks
+// (match_key, for 1- and 2-byte symbols, whose 4 symbols fit one 32- or
+// 64-bit compare) or per-row offset masks (4- and 8-byte symbols; 4% faster
+// than per-lane runs on the literal-heavy 4-byte field).
 template <int S> constexpr bool kRunSearch = S <= 2;
 
 // One chunk's work.
@@ -93,23 +94,6 @@ __device__ __forceinline__ typename SymType<S>::T vec_elem(const uint4& v, int e
     return (T)(w[e >> 1] >> (16 * (e & 1)));
   } else {
     return (T)(w[e >> 2] >> (8 * (e & 3)));
-  }
-}
-
-// 4 * S bytes (S = 1 or 2) from LDS at any byte address, read as aligned
-// dwords (wide LDS reads below dword alignment are slow) and funnel-shifted.
-template <int S>
-__device__ __forceinline__ typename SymType<4 * S>::T load4_sub(const void* p) {
-  const uint8_t* b = static_cast<const uint8_t*>(p);
-  const uint32_t sh = (uint32_t)(uintptr_t)b & 3u;
-  const uint32_t* w = reinterpret_cast<const uint32_t*>(__builtin_assume_aligned(b - sh, 4));
-  const uint32_t w0 = w[0], w1 = w[1];
-  const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, sh);
-  if constexpr (S == 1) {
-    return lo;
-  } else {
-    const uint32_t w2 = w[2];
-    return (uint64_t)lo | ((uint64_t)__builtin_amdgcn_alignbyte(w2, w1, sh) << 32);
   }
 }
 
@@ -394,23 +378,11 @@ __device__ __forceinline__ uint32_t search_token(const typename SymType<S>::T* w
       // this lane's window symbol for row r, column col: win[qb + r - (64 col + lane + 1)]
       const T* wbase = win + (int)qb - (int)lane - 1 - 64 * (WC - 1);
       T xr[4], wr[4][WC];
-      if constexpr (S <= 2) {
-        const auto xv = load4_sub<S>(win + qb);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) xr[r] = (T)(xv >> (8 * S * r));
+      for (int r = 0; r < 4; ++r) {
+        xr[r] = win[qb + r];
 #pragma unroll
-        for (int col = 0; col < WC; ++col) {
-          const auto wv = load4_sub<S>(wbase + 64 * (WC - 1 - col));
-#pragma unroll
-          for (int r = 0; r < 4; ++r) wr[r][col] = (T)(wv >> (8 * S * r));
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          xr[r] = win[qb + r];
-#pragma unroll
-          for (int col = 0; col < WC; ++col) wr[r][col] = wbase[r + 64 * (WC - 1 - col)];
-        }
+        for (int col = 0; col < WC; ++col) wr[r][col] = wbase[r + 64 * (WC - 1 - col)];
       }
       if (L + 4 <= 64) {
         // offsets d <= L (only d = L can still be present) all sit in column 0

@@ -259,3 +259,39 @@ def test_split_parse_matches_oracle(S, C, n_sym, kind):
         assert s == oracle.compress(x, S, C, W, MIN)
         st, d, n, canary = gpu_decompress(s, x.size)
         assert st == gpulz.GPULZ_OK and canary and d == x.tobytes()
+
+
+# Chunks without a pointer take a shortcut in the workgroup decoder (the
+# payload is the chunk). Random symbols with a long minimum match give such
+# chunks at every record alignment; the record sizes, flags and payloads
+# are then mutated and every verdict compared with the oracle's.
+@pytest.mark.parametrize("S,C,W,MIN", [(1, 250, 16, 6), (2, 300, 64, 2), (4, 256, 64, 2),
+                                       (8, 100, 32, 2)])
+def test_literal_only_chunks(S, C, W, MIN):
+    rng = random.Random(S * 131 + C)
+    n = 7 * C + C // 3
+    x = synth.uniform_bytes(n * S, seed=S + 300)
+    s = oracle.compress(x, S, C, W, MIN)
+    N = (n + C - 1) // C
+    lit_only = 64 + 8 * N + sum((min(C, n - i * C) + 7) // 8 + min(C, n - i * C) * S for i in range(N))
+    assert len(s) == lit_only  # no pointer anywhere
+    _say("literal-only chunks", S, C)
+    st, d, _, canary = gpu_decompress(s, x.size)
+    assert st == gpulz.GPULZ_OK and canary and d == x.tobytes()
+    muts = list(_mutations(s, rng, 30))
+    for k in range(N):  # each table entry's F or P off by one
+        for field, delta in ((0, 1), (0, -1), (4, 1), (4, -1)):
+            b = bytearray(s)
+            off = 64 + 8 * k + field
+            v = struct.unpack_from("<I", b, off)[0]
+            struct.pack_into("<I", b, off, (v + delta) & 0xFFFFFFFF)
+            muts.append(bytes(b))
+    for mut in muts:
+        cap = x.size + 64
+        ost, odata, _ = oracle.decompress_status(mut, capacity=cap)
+        gst, gdata, _, canary = gpu_decompress(mut, cap)
+        assert canary
+        if ost == oracle.OK:
+            assert gst == gpulz.GPULZ_OK and gdata == odata
+        else:
+            assert gst != gpulz.GPULZ_OK
