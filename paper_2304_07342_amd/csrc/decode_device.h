@@ -570,6 +570,62 @@ __device__ bool decode_chunk_block(const uint8_t* rec, const uint8_t* in_end, ui
   return true;
 }
 
+// 16 bytes starting sh bytes (0..3) past the dword at q (global memory),
+// funnel-shifted from dword reads that never reach in_end.
+__device__ __forceinline__ uint4 load_group(const uint32_t* q, uint32_t sh, const uint8_t* in_end) {
+  uint32_t d[5];
+  __builtin_memcpy(d, __builtin_assume_aligned(q, 4), 16);
+  d[4] = 0;
+  if (sh) {
+    // the fifth dword holds the group's last sh bytes; at the end of the
+    // stream it is read byte by byte
+    const uint8_t* q4 = reinterpret_cast<const uint8_t*>(q + 4);
+    if (q4 + 4 <= in_end) {
+      d[4] = q[4];
+    } else {
+      for (uint32_t b = 0; b < sh; ++b) d[4] |= (uint32_t)q4[b] << (8 * b);
+    }
+  }
+  return make_uint4(__builtin_amdgcn_alignbyte(d[1], d[0], sh), __builtin_amdgcn_alignbyte(d[2], d[1], sh),
+                    __builtin_amdgcn_alignbyte(d[3], d[2], sh), __builtin_amdgcn_alignbyte(d[4], d[3], sh));
+}
+
+// A record sized for c literals (F = ceil(c / 8) flag bytes, P = c S payload
+// bytes) whose flag bytes are all zero is valid and its payload is the chunk:
+// copy it straight from the stream to the output (dword-aligned 16-byte loads,
+// funnel-shifted by the payload's offset within a dword). Returns false
+// (uniformly), having written nothing, if any flag bit is set. Every dword
+// read holds a byte of the record; none reaches in_end.
+__device__ inline bool copy_literal_chunk(const uint8_t* rec, const uint8_t* in_end, uint32_t F,
+                                          uint32_t nb, uint8_t* dst) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t r0 = (uint32_t)((uintptr_t)rec & 3u);
+  const uint32_t* fw = reinterpret_cast<const uint32_t*>(rec - r0);
+  bool set = false;
+  for (uint32_t k = tid; 4 * k < r0 + F; k += kDecThreads) {
+    uint32_t v = 0;
+    const uint8_t* wk = reinterpret_cast<const uint8_t*>(fw + k);
+    if (wk + 4 <= in_end) {
+      v = fw[k];
+    } else {
+      for (uint32_t b = 0; wk + b < in_end; ++b) v |= (uint32_t)wk[b] << (8 * b);
+    }
+    if (4 * k < r0) v &= ~0u << (8 * r0);                // bytes before the record
+    const uint32_t in_f = r0 + F - 4 * k;                 // flag bytes in this dword, from its start
+    if (in_f < 4) v &= (1u << (8 * in_f)) - 1u;           // bytes after the flags
+    set = set || v != 0;
+  }
+  if (__syncthreads_or(set)) return false;
+  const uint8_t* src = rec + F;
+  const uint32_t sh = (uint32_t)((uintptr_t)src & 3u);
+  const uint32_t* sw = reinterpret_cast<const uint32_t*>(src - sh);
+  const uint32_t ng = ((uintptr_t)dst & 15u) == 0 ? nb / 16 : 0u;  // 16-byte groups
+  for (uint32_t k = tid; k < ng; k += kDecThreads)
+    *reinterpret_cast<uint4*>(dst + 16 * k) = load_group(sw + 4 * k, sh, in_end);
+  for (uint32_t b = 16 * ng + tid; b < nb; b += kDecThreads) dst[b] = src[b];
+  return true;
+}
+
 // Decode chunk i of a validated stream of in_bytes bytes with the whole
 // workgroup; false (uniformly) if it is corrupt. Chunks the workgroup
 // decoder does not take go to the wave decoder on wave 0.
@@ -583,6 +639,7 @@ __device__ inline bool decode_stream_chunk_block(const uint8_t* in, uint64_t in_
   const uint64_t cs = i * p.C;
   const uint32_t c = (uint32_t)min<uint64_t>(p.C, p.m - cs);
   uint8_t* dst = out + cs * p.S;
+  if (F == (c + 7) / 8 && P == c * p.S && copy_literal_chunk(rec, in + in_bytes, F, P, dst)) return true;
   if (fits_block(c, p.S, F, P)) {
     switch (p.S) {
       case 1: return decode_chunk_block<1>(rec, in + in_bytes, F, P, c, p.W, p.MIN, dst, sm);
