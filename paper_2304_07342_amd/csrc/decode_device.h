@@ -620,8 +620,20 @@ __device__ inline bool copy_literal_chunk(const uint8_t* rec, const uint8_t* in_
   const uint32_t sh = (uint32_t)((uintptr_t)src & 3u);
   const uint32_t* sw = reinterpret_cast<const uint32_t*>(src - sh);
   const uint32_t ng = ((uintptr_t)dst & 15u) == 0 ? nb / 16 : 0u;  // 16-byte groups
-  for (uint32_t k = tid; k < ng; k += kDecThreads)
-    *reinterpret_cast<uint4*>(dst + 16 * k) = load_group(sw + 4 * k, sh, in_end);
+  // four groups per thread in flight: all loads, then all stores
+  for (uint32_t k0 = tid; k0 < ng; k0 += 4 * kDecThreads) {
+    uint4 g[4];
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+      const uint32_t k = k0 + j * kDecThreads;
+      if (k < ng) g[j] = load_group(sw + 4 * k, sh, in_end);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+      const uint32_t k = k0 + j * kDecThreads;
+      if (k < ng) *reinterpret_cast<uint4*>(dst + 16 * k) = g[j];
+    }
+  }
   for (uint32_t b = 16 * ng + tid; b < nb; b += kDecThreads) dst[b] = src[b];
   return true;
 }
