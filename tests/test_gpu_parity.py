@@ -286,6 +286,17 @@ def test_literal_only_chunks(S, C, W, MIN):
             v = struct.unpack_from("<I", b, off)[0]
             struct.pack_into("<I", b, off, (v + delta) & 0xFFFFFFFF)
             muts.append(bytes(b))
+        # size moves that keep the table's sum: flag bytes <-> payload bytes in
+        # one entry, and payload bytes between neighbouring entries
+        moves = [((64 + 8 * k, 1), (68 + 8 * k, -1)), ((64 + 8 * k, -1), (68 + 8 * k, 1))]
+        if k + 1 < N:
+            moves += [((68 + 8 * k, 1), (68 + 8 * k + 8, -1)), ((68 + 8 * k, -1), (68 + 8 * k + 8, 1))]
+        for (o1, d1), (o2, d2) in moves:
+            b = bytearray(s)
+            for off, delta in ((o1, d1), (o2, d2)):
+                v = struct.unpack_from("<I", b, off)[0]
+                struct.pack_into("<I", b, off, (v + delta) & 0xFFFFFFFF)
+            muts.append(bytes(b))
     for mut in muts:
         cap = x.size + 64
         ost, odata, _ = oracle.decompress_status(mut, capacity=cap)
