@@ -306,3 +306,37 @@ def test_literal_only_chunks(S, C, W, MIN):
             assert gst == gpulz.GPULZ_OK and gdata == odata
         else:
             assert gst != gpulz.GPULZ_OK
+
+
+# The exact search for 1- and 2-byte symbols (equality steps over offset
+# masks, lengths from the last step) on the inputs that stress it: two- and
+# three-symbol alphabets, constant and periodic runs, windows on both sides of
+# each 64-offset column, lengths near the 255 cap and chunk ends, both the
+# split-parse launch (few chunks) and the one-wave launch (many chunks).
+def test_narrow_symbol_search_against_oracle():
+    rng = random.Random(2024)
+    cases = []
+    for k in range(120):
+        S = rng.choice([1, 2])
+        C = rng.choice([1, 7, 64, 100, 257, 1000, 2048, 4096])
+        W = rng.choice([1, 2, 3, 4, 5, 31, 63, 64, 65, 127, 128, 129, 200, 255, 256])
+        MIN = rng.choice([1, 2, 3, 4, 7])
+        cases.append((S, C, W, MIN, rng.randint(1, 6000), k))
+    for k in range(4):  # more than 1024 chunks: the one-wave launch
+        cases.append((1 + k % 2, 64, rng.choice([63, 64, 65, 256]), 2, 70000, 500 + k))
+    for S, C, W, MIN, m, seed in cases:
+        kind = seed % 4
+        if kind == 0:
+            x = synth.small_alphabet(m, S, seed=seed, alphabet=2)
+        elif kind == 1:
+            x = synth.small_alphabet(m, S, seed=seed, alphabet=3)
+        elif kind == 2:
+            x = synth.runs(m, S, seed=seed)
+        else:
+            x = synth.mixed(m * S, S, seed=seed)
+        _say("narrow search", S, C, W, MIN, x.size, seed)
+        ref = oracle.compress(x, S, C, W, MIN)
+        st, s, _, canary = gpu_compress(x, S, C, W, MIN)
+        assert st == gpulz.GPULZ_OK and canary and s == ref, (S, C, W, MIN, seed)
+        dst, d, _, canary = gpu_decompress(s, x.size)
+        assert dst == gpulz.GPULZ_OK and canary and d == np.ascontiguousarray(x).tobytes()
