@@ -146,15 +146,28 @@ def test_empty_and_sub_symbol_inputs(n, S):
 
 
 def test_bound_is_reached_by_worst_cases():
-    # S=1, MIN=1 on "ABABAB..." after the first two symbols every position is a
-    # length-1 or longer pointer; the bound must hold for all-literal and
-    # all-pointer worst cases.
+    # The bound never fails on random inputs ...
     for S, MIN in [(1, 1), (1, 2), (2, 1), (4, 2), (8, 3)]:
         x = bytes(random.Random(S).randrange(256) for _ in range(S * 5000))
         assert len(oracle.compress(x, S, 333, 256, MIN)) <= oracle.compress_bound(len(x), S, 333, MIN)
-    x = bytes([0, 1] * 3000)
-    s = oracle.compress(x, 1, 1000, 1, 1)  # W=1: only d=1, L=1 -> every token a pointer
-    assert len(s) <= oracle.compress_bound(len(x), 1, 1000, 1)
+    # ... and is met with equality by its all-literal case: symbols that are
+    # all distinct (strictly increasing u32) have no match, so every chunk of
+    # c symbols costs ceil(c/8) + 4c bytes.
+    x = np.arange(1, 2 * 333 + 57, dtype=np.uint32).tobytes() + b"\x07\x08"
+    assert len(oracle.compress(x, 4, 333, 256, 2)) == oracle.compress_bound(len(x), 4, 333, 2)
+    # The S = 1, MIN = 1 case prices every token as a 2-byte pointer of length
+    # 1. With W = 1 only d = 1 exists and L <= d = 1, so on constant bytes
+    # every token after a chunk's first (a literal, the window being empty)
+    # is exactly such a pointer: the stream is the bound less one byte per
+    # chunk (ragged last chunk included).
+    for n, C in [(3000, 1000), (2999, 1000), (1, 7), (64, 8)]:
+        x = b"\x5a" * n
+        s = oracle.compress(x, 1, C, 1, 1)
+        N = -(-n // C)
+        assert len(s) == oracle.compress_bound(n, 1, C, 1) - N
+        toks = [(L, d) for L, d in oracle.parse_chunk(x[:min(C, n)], 1, 1, 1)]
+        assert toks == [(0, 0)] + [(1, 1)] * (min(C, n) - 1)
+        assert oracle.decompress(s) == x
 
 
 def test_out_of_space_reports_required_size():
