@@ -12,6 +12,8 @@ window 256, minimum match 2 (seed 1).
 Other workloads (--workload), each printing its own JSON lines:
   small   1 MiB of uint16 Laplace codes (launch-latency bound): median of
           single launches and of graph replays;
+  dense   256 MiB each of Zipf bytes and uint16 Laplace codes (match-dense:
+          the exact search runs at almost every token);
   scan    match policy 1 (the paper's single window pass) beside policy 0
           on the field and on the 1 MiB codes;
   adaptive  the adaptive symbol width / window rule and its levels on each
@@ -244,6 +246,58 @@ def run_small(args):
                       "single_launch_GBps": round(n / single / 1e6, 3),
                       "graph_replay_ms_p50": round(graph, 4),
                       "graph_replay_GBps": round(n / graph / 1e6, 3)}), flush=True)
+
+
+# Match-dense inputs at the parameters the autotuner picks for them (1 GiB
+# width sweep): (kind, seed, S, C, W, MIN, waves per chunk).
+DENSE_INPUTS = (("zipf-u8", 201, 1, 2048, 256, 2, 1), ("laplace-u16", 202, 2, 4096, 256, 2, 4))
+
+
+def run_dense(args):
+    """256 MiB each of Zipf bytes and uint16 Laplace codes, the match-dense
+    inputs where the exact search runs at almost every token: compress GB/s,
+    ratio and the encode kernel's average time (HIP events on the call's
+    stream)."""
+    import torch
+    from paper_2304_07342_amd import gpulz, synth
+    size = args.dense_mib << 20
+    for kind, seed, S, C, W, MIN, waves in DENSE_INPUTS:
+        log(f"dense {kind} {size >> 20} MiB")
+        x = torch.from_numpy(synth.POOL_KINDS[kind][1](size, seed)[:size]).to("cuda")
+        saved = gpulz.gpulz_default_params(S)
+        gpulz.gpulz_set_default_params(S, saved[0], saved[1], saved[2], waves)
+        try:
+            comp = gpulz.Compressor(size, S, C, W, MIN)
+            for _ in range(args.warmup):
+                comp.compress_async(x)
+            nbytes, status = comp.result()
+            assert status == gpulz.GPULZ_OK
+            stream = torch.cuda.current_stream()
+            gpulz.gpulz_profile_enable(True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(args.steps):
+                comp.compress_async(x)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            prof = gpulz.gpulz_profile_read()
+            gpulz.gpulz_profile_enable(False)
+        finally:
+            gpulz.gpulz_set_default_params(S, *saved)
+        ms = e0.elapsed_time(e1) / args.steps
+        d = gpulz.decompress(comp.out[:nbytes])
+        if not torch.equal(d, x):
+            raise SystemExit(f"round trip mismatch for {kind}")
+        kernel_ms = {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items() if v[1]}
+        print(json.dumps({"metric": "compress GB/s (input) + ratio", "workload": f"dense-{kind}",
+                          "symbol_bytes": S, "input_bytes": size, "value": round(size / ms / 1e6, 3),
+                          "unit": "GB/s", "ms_per_step": round(ms, 4),
+                          "ratio": round(size / nbytes, 4), "chunk_symbols": C, "window": W,
+                          "min_match": MIN, "waves_per_chunk": waves,
+                          "kernel_avg_ms": kernel_ms}), flush=True)
+        del x, comp, d
+        torch.cuda.empty_cache()
 
 
 def run_scan(args):
@@ -576,9 +630,10 @@ def run_batch(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="field",
-                    choices=["field", "small", "scan", "sweep", "adaptive", "host", "entropy",
-                             "batch", "serve"])
+                    choices=["field", "small", "dense", "scan", "sweep", "adaptive", "host",
+                             "entropy", "batch", "serve"])
     ap.add_argument("--sweep-bytes", type=int, default=1 << 30)
+    ap.add_argument("--dense-mib", type=int, default=256)
     ap.add_argument("--nbufs", type=int, default=4096)
     ap.add_argument("--pool-mib", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -605,6 +660,8 @@ def main():
 
     if args.workload == "small":
         return run_small(args)
+    if args.workload == "dense":
+        return run_dense(args)
     if args.workload == "scan":
         return run_scan(args)
     if args.workload == "adaptive":

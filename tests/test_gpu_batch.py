@@ -150,3 +150,18 @@ def test_batch_large_buffers_span_many_chunks():
     bc.run()
     for x, S, (st, s) in zip(bufs, widths, bc.results()):
         assert st == gpulz.GPULZ_OK and s.cpu().numpy().tobytes() == _expected(x, S, PARAMS)
+
+
+# Every waves-per-chunk setting (1, 2 or 4 wavefronts per chunk encoder) for
+# every width, passed explicitly: the bytes are the oracle's.
+@pytest.mark.parametrize("waves", [1, 2, 4])
+def test_batch_explicit_waves_match_oracle(waves):
+    bufs, widths = _make_batch(40 + waves, 24, 70000)
+    params = {S: tuple(PARAMS[S]) + (waves,) for S in PARAMS}
+    _say("batch waves", waves)
+    ins = [to_device(b)[: b.size] for b in bufs]
+    bc = gpulz.BatchCompressor(ins, widths, params)
+    bc.run()
+    for x, S, (st, s) in zip(bufs, widths, bc.results()):
+        assert st == gpulz.GPULZ_OK
+        assert s.cpu().numpy().tobytes() == _expected(x, S, PARAMS), (S, x.size, waves)

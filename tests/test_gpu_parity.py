@@ -92,11 +92,10 @@ def test_codes_1mib_full():
     assert st == gpulz.GPULZ_OK and d == x.tobytes()
 
 
-def test_field_256mib_sampled_chunks():
-    """256 MiB float32 field at full size with the benchmark's parameters.
-    Chunks are independent, so each sampled chunk's table entry and record
-    are checked against the oracle run on that chunk alone; the header,
-    table sums and an exact GPU round trip cover the rest."""
+def test_field_256mib_full_stream():
+    """256 MiB float32 field at full size with the benchmark's parameters and
+    launch: the whole stream (all 16,384 chunks) equals the oracle's, computed
+    over 16 threads, and the GPU round trip is exact."""
     import torch
     cfg = synth.WORKLOADS[synth.FIELD_256MIB]
     S, C, W, MIN = cfg["S"], cfg["C"], cfg["W"], cfg["MIN"]
@@ -108,20 +107,14 @@ def test_field_256mib_sampled_chunks():
     size, status = c.result()
     assert status == gpulz.GPULZ_OK
     s = c.out[:size].cpu().numpy().tobytes()
-    n, SS, total = gpulz.gpulz_peek_header(s[:64])
-    assert (n, SS, total) == (x.size, S, len(s))
-    N = -(-(x.size // S) // C)
-    table = np.frombuffer(s, dtype=np.uint32, count=2 * N, offset=64).reshape(N, 2)
-    offs = 64 + 8 * N + np.concatenate([[0], np.cumsum(table.sum(axis=1).astype(np.int64))])
-    assert offs[-1] == len(s)
-    rng = np.random.default_rng(7)
-    sample = sorted(set(rng.choice(N, size=24, replace=False).tolist()) | {0, N - 1})
-    for i in sample:
-        chunk = x[i * C * S:(i + 1) * C * S]
-        ref = oracle.compress(chunk, S, C, W, MIN)
-        F, P = struct.unpack_from("<II", ref, 64)
-        assert (F, P) == tuple(table[i]), i
-        assert s[offs[i]:offs[i + 1]] == ref[72:72 + F + P], i
+    _say("field 256 MiB: oracle over 16 threads")
+    ref = oracle.compress(x, S, C, W, MIN, threads=16)
+    assert len(s) == len(ref)
+    if s != ref:
+        a = np.frombuffer(s, dtype=np.uint8)
+        b = np.frombuffer(ref, dtype=np.uint8)
+        first = int(np.flatnonzero(a != b)[0])
+        raise AssertionError(f"stream differs from the oracle first at byte {first}")
     d = gpulz.decompress(c.out[:size])
     assert torch.equal(d, d_in)
 
@@ -187,10 +180,11 @@ def test_decoder_rejects_what_the_oracle_rejects(seed):
         ost, odata, _ = oracle.decompress_status(mut, capacity=cap)
         gst, gdata, _, canary = gpu_decompress(mut, cap)
         assert canary
+        # the oracle's status codes use the library's numbering: the two must
+        # give the same verdict (OK, CORRUPT or OUT_OF_SPACE)
+        assert gst == ost
         if ost == oracle.OK:
-            assert gst == gpulz.GPULZ_OK and gdata == odata
-        else:
-            assert gst != gpulz.GPULZ_OK
+            assert gdata == odata
 
 
 # Chunks beyond the workgroup decoder's limits (more than 4096 symbols, or
@@ -208,23 +202,30 @@ def test_wave_decoder_rejects_what_the_oracle_rejects(S, C):
         ost, odata, _ = oracle.decompress_status(mut, capacity=cap)
         gst, gdata, _, canary = gpu_decompress(mut, cap)
         assert canary
+        # the oracle's status codes use the library's numbering: the two must
+        # give the same verdict (OK, CORRUPT or OUT_OF_SPACE)
+        assert gst == ost
         if ost == oracle.OK:
-            assert gst == gpulz.GPULZ_OK and gdata == odata
-        else:
-            assert gst != gpulz.GPULZ_OK
+            assert gdata == odata
 
 
+# 70000 symbols at C = 64 are 1094 chunks, more than the split-parse launch
+# takes (1024 for S <= 2, 512 for S >= 4), so the per-chunk encoder runs with
+# each waves-per-chunk setting; every result is compared with the oracle.
 @pytest.mark.parametrize("S", [1, 2, 4, 8])
 def test_waves_per_chunk_does_not_change_bytes(S):
-    x = synth.mixed(200000, S, seed=S + 40)
+    n_sym, C = 70000, 64
+    x = synth.mixed(n_sym * S, S, seed=S + 40)
+    assert -(-n_sym // C) > 1024
     saved = gpulz.gpulz_default_params(S)
-    _say("waves", S)
     try:
-        outs = set()
-        for w in (1, 2, 4):
-            gpulz.gpulz_set_default_params(S, saved[0], saved[1], saved[2], w)
-            outs.add(gpu_compress(x, S, 1024, 200, 2)[1])
-        assert len(outs) == 1 and outs.pop() == oracle.compress(x, S, 1024, 200, 2)
+        for W, MIN in ((200, 2), (64, 1)):
+            ref = oracle.compress(x, S, C, W, MIN)
+            for w in (1, 2, 4):
+                _say("waves", S, W, MIN, w)
+                gpulz.gpulz_set_default_params(S, saved[0], saved[1], saved[2], w)
+                st, s, _, canary = gpu_compress(x, S, C, W, MIN)
+                assert st == gpulz.GPULZ_OK and canary and s == ref, (S, W, MIN, w)
     finally:
         gpulz.gpulz_set_default_params(S, *saved)
 
@@ -302,10 +303,11 @@ def test_literal_only_chunks(S, C, W, MIN):
         ost, odata, _ = oracle.decompress_status(mut, capacity=cap)
         gst, gdata, _, canary = gpu_decompress(mut, cap)
         assert canary
+        # the oracle's status codes use the library's numbering: the two must
+        # give the same verdict (OK, CORRUPT or OUT_OF_SPACE)
+        assert gst == ost
         if ost == oracle.OK:
-            assert gst == gpulz.GPULZ_OK and gdata == odata
-        else:
-            assert gst != gpulz.GPULZ_OK
+            assert gdata == odata
 
 
 # The exact search for 1- and 2-byte symbols (equality steps over offset

@@ -1,5 +1,6 @@
 """Serving on the GPU: every result produced in the mix of a continuous-
-batching run equals the same request run alone (byte for byte)."""
+batching run equals the same request run alone (byte for byte), and every
+compress result equals the oracle's stream for its bytes and parameters."""
 import numpy as np
 import pytest
 
@@ -35,7 +36,11 @@ def test_results_identical_alone_and_in_the_mix():
         assert r.status == gpulz.GPULZ_OK, r
         got = r.result.cpu().numpy().tobytes()
         if r.op == serve.COMPRESS:
-            alone = gpulz.compress(r.src, r.symbol_bytes, *gpulz.gpulz_default_params(r.symbol_bytes)[:3])
+            C, W, MIN, _ = gpulz.gpulz_default_params(r.symbol_bytes)
+            alone = gpulz.compress(r.src, r.symbol_bytes, C, W, MIN)
+            # and the oracle on the same bytes with the width's parameters
+            src = r.src.cpu().numpy()
+            assert got == oracle.compress(src, r.symbol_bytes, C, W, MIN, threads=8), r.rid
         else:
             alone = gpulz.decompress(r.src)
         assert got == alone.cpu().numpy().tobytes(), r.rid
