@@ -49,27 +49,38 @@ HBM_PEAK_GBPS = 8000.0
 # same counter reads for a device copy of the 256 MiB input (FETCH_SIZE reads
 # half the copied bytes: factor 2.0; WRITE_SIZE reads them exactly: 1.0).
 # Valid only for the encoder sources they were taken on (sha256 below).
+# "prep" is the compress call's preparation kernel (look-back descriptors
+# and tickets zeroed); the step is prep + encode.
 ENCODE_COUNTERS = {
-    "sources_sha256": "925f2fe49d88eb3b20f220995098d52f31210e85b89f566a18e4798c39b72061",
-    "fetch_kib": 131155.0, "fetch_scale": 2.0,
-    "write_kib": 271821.0, "write_scale": 1.0,
+    "sources_sha256": None,
+    "fetch_kib": None, "write_kib": None,
+    "prep_fetch_kib": None, "prep_write_kib": None,
+    "fetch_scale": 2.0, "write_scale": 1.0,
 }
 ENCODE_SOURCES = ("paper_2304_07342_amd/csrc/lz_encode.hip", "paper_2304_07342_amd/csrc/encode_device.h",
-                  "paper_2304_07342_amd/csrc/wave.h", "paper_2304_07342_amd/csrc/gpulz_internal.h")
+                  "paper_2304_07342_amd/csrc/stream_device.h", "paper_2304_07342_amd/csrc/wave.h",
+                  "paper_2304_07342_amd/csrc/gpulz_internal.h")
 
 
-def encode_traffic_bytes():
-    """Counter-derived HBM bytes per encode launch, or None if the encoder
-    has changed since the counters were taken."""
+def encoder_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
     for f in ENCODE_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()
+
+
+def encode_traffic_bytes():
+    """Counter-derived HBM bytes per encode launch and per whole step (prep +
+    encode), or (None, None) if the encoder has changed since the counters
+    were taken."""
     c = ENCODE_COUNTERS
-    if h.hexdigest() != c["sources_sha256"]:
-        return None
-    return int((c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024)
+    if c["sources_sha256"] is None or encoder_sources_sha256() != c["sources_sha256"]:
+        return None, None
+    enc = (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024
+    prep = (c["prep_fetch_kib"] * c["fetch_scale"] + c["prep_write_kib"] * c["write_scale"]) * 1024
+    return int(enc), int(enc + prep)
 # 256 CUs x 64 lanes x 2.4 GHz: one 32-bit compare per lane per clock.
 ALU_PEAK_TCMP = 256 * 64 * 2.4e9 / 1e12
 
@@ -83,6 +94,33 @@ def window_compares(m: int, C: int, W: int) -> int:
         return W * (W + 1) // 2 + (c - 1 - W) * W
     full, last = divmod(m, C)
     return full * per_chunk(C) + (per_chunk(last) if last else 0)
+
+
+def executed_hit_compares(m: int, C: int, W: int, S: int, MIN: int) -> int:
+    """Symbol compares the encoder's hit phase executes: each lane owns V =
+    16 / S positions of a 64 V block and compares every tested position
+    (even ones when MIN >= 2) with W window offsets, masked or not. The
+    exact searches at candidate positions come on top (data-dependent, rare
+    on the field)."""
+    V = 16 // S
+    step = 2 if MIN >= 2 else 1
+
+    def per_chunk(c):
+        blocks = -(-c // (64 * V))
+        return blocks * 64 * (V // step) * W
+    full, last = divmod(m, C)
+    return full * per_chunk(C) + (per_chunk(last) if last else 0)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_threads() -> int:
@@ -107,7 +145,7 @@ def cpu_baseline(x: np.ndarray, S: int, C: int, W: int, MIN: int, sample_bytes: 
     dt = time.perf_counter() - t0
     kind = "single-threaded C oracle" if threads == 1 else f"C oracle over {threads} threads"
     return {"value": round(sample.size / dt / 1e9, 6), "unit": "GB/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": f"first {sample.size >> 20} MiB ({sample.size // (C * S)} chunks) of the same "
                       f"input, {kind}, {dt:.1f} s"}
 
@@ -194,7 +232,7 @@ def run_sweep(args):
         torch.cuda.empty_cache()
 
 
-def run_small(args):
+def small_leg(args):
     """1 MiB of uint16 codes: launch-latency bound, so report the median of
     single launches and of graph replays of the same call."""
     import torch
@@ -239,13 +277,17 @@ def run_small(args):
     d = gpulz.decompress(comp.out[:size])
     if not torch.equal(d, x):
         raise SystemExit("round trip mismatch")
-    print(json.dumps({"metric": "compress GB/s (input) + ratio", "workload": cfg["name"],
-                      "input_bytes": n, "ratio": round(n / size, 4), "symbol_bytes": S,
-                      "chunk_symbols": C, "window": W, "min_match": MIN, "runs": reps,
-                      "single_launch_ms_p50": round(single, 4),
-                      "single_launch_GBps": round(n / single / 1e6, 3),
-                      "graph_replay_ms_p50": round(graph, 4),
-                      "graph_replay_GBps": round(n / graph / 1e6, 3)}), flush=True)
+    return {"metric": "compress GB/s (input) + ratio", "workload": cfg["name"],
+            "input_bytes": n, "ratio": round(n / size, 4), "symbol_bytes": S,
+            "chunk_symbols": C, "window": W, "min_match": MIN, "runs": reps,
+            "single_launch_ms_p50": round(single, 4),
+            "single_launch_GBps": round(n / single / 1e6, 3),
+            "graph_replay_ms_p50": round(graph, 4),
+            "graph_replay_GBps": round(n / graph / 1e6, 3)}
+
+
+def run_small(args):
+    print(json.dumps(small_leg(args)), flush=True)
 
 
 # Match-dense inputs at the parameters the autotuner picks for them (1 GiB
@@ -253,51 +295,60 @@ def run_small(args):
 DENSE_INPUTS = (("zipf-u8", 201, 1, 2048, 256, 2, 1), ("laplace-u16", 202, 2, 4096, 256, 2, 4))
 
 
-def run_dense(args):
-    """256 MiB each of Zipf bytes and uint16 Laplace codes, the match-dense
-    inputs where the exact search runs at almost every token: compress GB/s,
-    ratio and the encode kernel's average time (HIP events on the call's
-    stream)."""
+def dense_leg(args, kind, seed, S, C, W, MIN, waves, size):
+    """One match-dense input: compress GB/s, ratio, the encode kernel's
+    average time (HIP events on the call's stream) and its algorithmic
+    compare rate against the ALU compare peak."""
     import torch
     from paper_2304_07342_amd import gpulz, synth
-    size = args.dense_mib << 20
+    log(f"dense {kind} {size >> 20} MiB")
+    x = torch.from_numpy(synth.POOL_KINDS[kind][1](size, seed)[:size]).to("cuda")
+    saved = gpulz.gpulz_default_params(S)
+    gpulz.gpulz_set_default_params(S, saved[0], saved[1], saved[2], waves)
+    try:
+        comp = gpulz.Compressor(size, S, C, W, MIN)
+        for _ in range(max(1, args.warmup)):
+            comp.compress_async(x)
+        nbytes, status = comp.result()
+        assert status == gpulz.GPULZ_OK
+        stream = torch.cuda.current_stream()
+        gpulz.gpulz_profile_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        steps = max(1, min(args.steps, 10))
+        e0.record(stream)
+        for _ in range(steps):
+            comp.compress_async(x)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        prof = gpulz.gpulz_profile_read()
+        gpulz.gpulz_profile_enable(False)
+    finally:
+        gpulz.gpulz_set_default_params(S, *saved)
+    ms = e0.elapsed_time(e1) / steps
+    d = gpulz.decompress(comp.out[:nbytes])
+    if not torch.equal(d, x):
+        raise SystemExit(f"round trip mismatch for {kind}")
+    kernel_ms = {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items() if v[1]}
+    enc_ms = kernel_ms.get("encode", ms)
+    cmp = window_compares(size // S, C, W)
+    out = {"workload": f"dense-{kind}-{size >> 20}MiB", "symbol_bytes": S, "input_bytes": size,
+           "value": round(size / ms / 1e6, 3), "unit": "GB/s", "ms_per_step": round(ms, 4),
+           "ratio": round(size / nbytes, 4), "chunk_symbols": C, "window": W, "min_match": MIN,
+           "waves_per_chunk": waves, "kernel_avg_ms": kernel_ms,
+           "compare_peak_frac": round(cmp / (enc_ms / 1e3) / 1e12 / ALU_PEAK_TCMP, 4)}
+    del x, comp, d
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_dense(args):
+    """256 MiB each of Zipf bytes and uint16 Laplace codes, the match-dense
+    inputs where the exact search runs at almost every token."""
     for kind, seed, S, C, W, MIN, waves in DENSE_INPUTS:
-        log(f"dense {kind} {size >> 20} MiB")
-        x = torch.from_numpy(synth.POOL_KINDS[kind][1](size, seed)[:size]).to("cuda")
-        saved = gpulz.gpulz_default_params(S)
-        gpulz.gpulz_set_default_params(S, saved[0], saved[1], saved[2], waves)
-        try:
-            comp = gpulz.Compressor(size, S, C, W, MIN)
-            for _ in range(args.warmup):
-                comp.compress_async(x)
-            nbytes, status = comp.result()
-            assert status == gpulz.GPULZ_OK
-            stream = torch.cuda.current_stream()
-            gpulz.gpulz_profile_enable(True)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            e0.record(stream)
-            for _ in range(args.steps):
-                comp.compress_async(x)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            prof = gpulz.gpulz_profile_read()
-            gpulz.gpulz_profile_enable(False)
-        finally:
-            gpulz.gpulz_set_default_params(S, *saved)
-        ms = e0.elapsed_time(e1) / args.steps
-        d = gpulz.decompress(comp.out[:nbytes])
-        if not torch.equal(d, x):
-            raise SystemExit(f"round trip mismatch for {kind}")
-        kernel_ms = {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items() if v[1]}
-        print(json.dumps({"metric": "compress GB/s (input) + ratio", "workload": f"dense-{kind}",
-                          "symbol_bytes": S, "input_bytes": size, "value": round(size / ms / 1e6, 3),
-                          "unit": "GB/s", "ms_per_step": round(ms, 4),
-                          "ratio": round(size / nbytes, 4), "chunk_symbols": C, "window": W,
-                          "min_match": MIN, "waves_per_chunk": waves,
-                          "kernel_avg_ms": kernel_ms}), flush=True)
-        del x, comp, d
-        torch.cuda.empty_cache()
+        leg = dense_leg(args, kind, seed, S, C, W, MIN, waves, args.dense_mib << 20)
+        leg["metric"] = "compress GB/s (input) + ratio"
+        print(json.dumps(leg), flush=True)
 
 
 def run_scan(args):
@@ -556,7 +607,9 @@ def run_entropy(args):
         "cpu_baseline": cpu}), flush=True)
 
 
-def run_batch(args):
+def batch_leg(args):
+    """4096 buffers (log-uniform sizes, mixed widths): one graph-captured
+    gpulz_compress_batch replay against one gpulz_compress per buffer."""
     import torch
     from paper_2304_07342_amd import gpulz, synth
     pool_bytes = args.pool_mib << 20
@@ -615,8 +668,8 @@ def run_batch(args):
         if sizes[i] != s.numel() or not torch.equal(outs[i][:sizes[i]], s):
             raise SystemExit(f"batched and plain streams differ for buffer {i}")
     pct = lambda v, q: v[min(len(v) - 1, int(q * len(v)))]
-    print(json.dumps({
-        "metric": "batched GB/s and p99 latency vs plain", "workload": "batch-4096",
+    out = {
+        "metric": "batched GB/s and p99 latency vs plain", "workload": f"batch-{len(spec)}",
         "nbufs": len(spec), "input_bytes": total, "stream_bytes": z, "ratio": round(total / z, 4),
         "batched_GBps": round(total / batched_ms / 1e6, 3), "batched_ms": round(batched_ms, 3),
         "plain_GBps": round(total / plain_ms / 1e6, 3), "plain_ms": round(plain_ms, 3),
@@ -624,7 +677,14 @@ def run_batch(args):
         "batched_completion_ms": {"p50": round(batched_ms, 3), "p99": round(batched_ms, 3)},
         "plain_completion_ms": {"p50": round(pct(done, 0.5), 3), "p99": round(pct(done, 0.99), 3)},
         "params": {str(S): list(p) for S, p in params.items()},
-        "autotune_GBps": {str(S): round(v["GBps"], 2) for S, v in tuned.items()}}), flush=True)
+        "autotune_GBps": {str(S): round(v["GBps"], 2) for S, v in tuned.items()}}
+    del bc, outs, ws, pools, inputs
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_batch(args):
+    print(json.dumps(batch_leg(args)), flush=True)
 
 
 def main():
@@ -649,6 +709,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-mib", type=int, default=128)
     ap.add_argument("--skip-decompress", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the field compression (no config 0, dense uint16 or batch keys)")
+    ap.add_argument("--no-batch", action="store_true", help="no batch key")
     ap.add_argument("--profile-copy", action="store_true",
                     help="end with one untimed device copy of the input (a known-size "
                          "reference for hardware byte counters)")
@@ -743,9 +806,11 @@ def main():
     enc_avg_ms = enc_ms / max(1, enc_launches)
     m = n // S
     compares = window_compares(m, C, W)
+    executed = executed_hit_compares(m, C, W, S, MIN)
     achieved = compares / (enc_avg_ms / 1e3) / 1e12
     kernel_ms = {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items() if v[1]}
     value = n / (ms_step / 1e3) / 1e9
+    traffic, step_traffic = encode_traffic_bytes()
 
     result = {
         "metric": "compress GB/s (input) + ratio at 1 GPU; batched GB/s and p99 latency vs plain",
@@ -769,11 +834,19 @@ def main():
         "decompress_GBps": round(dec_gbps, 3) if dec_gbps else None,
         "kernel_avg_ms": kernel_ms,
         "hbm_frac_whole_step": round((n + size) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
-        "roofline": {"bound": "alu", "kernel": "encode_kernel<4,4> (match search + parse + encode)",
+        "roofline": {"bound": "alu",
+                     "kernel": "encode_kernel<4,4> (match search, parse, look-back, record write-out)",
                      "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TCMP, 3),
                      "unit": "Tcmp/s", "frac": round(achieved / ALU_PEAK_TCMP, 4),
-                     "traffic": encode_traffic_bytes(), "compares_per_launch": compares,
-                     "hbm_algorithmic_bytes_per_launch": n + size},
+                     "achieved_counts": "algorithmic compares: every position against each of "
+                                        "its min(j, W) window offsets",
+                     "compares_per_launch": compares,
+                     "executed_hit_compares_per_launch": executed,
+                     "executed_frac": round(executed / (enc_avg_ms / 1e3) / 1e12 / ALU_PEAK_TCMP, 4),
+                     "traffic": traffic,
+                     "hbm_algorithmic_bytes_per_launch": n + size,
+                     "hbm_frac_encode": round((n + size) / (enc_avg_ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)},
+        "step_traffic": step_traffic,
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
@@ -785,6 +858,19 @@ def main():
         ref = torch.empty_like(d_in)
         ref.copy_(d_in)
         torch.cuda.synchronize()
+    if not args.no_extras:
+        # the other workloads the metric names, each as one key of this line
+        del comp, d_in
+        torch.cuda.empty_cache()
+        print("[bench] config 0: 1 MiB uint16 codes", file=sys.stderr, flush=True)
+        result["small"] = small_leg(args)
+        kind, seed, S2, C2, W2, MIN2, waves2 = DENSE_INPUTS[1]
+        result["dense_u16"] = dense_leg(args, kind, seed, S2, C2, W2, MIN2, waves2, 256 << 20)
+        if not args.no_batch:
+            print("[bench] config 3: batch of 4096 buffers", file=sys.stderr, flush=True)
+            bargs = argparse.Namespace(**vars(args))
+            bargs.steps = 1
+            result["batch"] = batch_leg(bargs)
     print(json.dumps(result), flush=True)
 
 

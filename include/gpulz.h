@@ -96,14 +96,23 @@ gpulz_status gpulz_compress_workspace_size(uint64_t nbytes, uint32_t symbol_byte
  *   out_capacity  bytes available at d_out
  *   d_out_bytes   device u64: receives the stream size (also when it does
  *                 not fit)
- *   d_status      device i32: GPULZ_OK, or GPULZ_ERR_OUT_OF_SPACE if the
- *                 stream is larger than out_capacity (then nothing is
- *                 written to d_out)
+ *   d_status      device i32: GPULZ_OK; GPULZ_ERR_OUT_OF_SPACE if the
+ *                 stream is larger than out_capacity (then no byte at or
+ *                 past out_capacity is written and d_out's contents are
+ *                 unspecified); GPULZ_ERR_HIP if a device-side wait of the
+ *                 record-offset look-back gave up (not expected in use)
  *   d_workspace   at least gpulz_compress_workspace_size bytes
+ * The call launches one small preparation kernel and then one chunk-encoder
+ * launch per 2^22 chunks: every chunk finds its record offset by decoupled
+ * look-back over the sizes its predecessors publish (the global prefix sum
+ * of section 3.2.2) and writes its table entry and record once, at the final
+ * place (section 3.3.4's compaction needs no pass of its own). Inputs of
+ * more than 2^27 chunks give GPULZ_ERR_UNSUPPORTED.
  * The chunk encoder runs with the waves_per_chunk of the width's defaults
  * (gpulz_default_params); that changes speed, never the bytes.
  * Asynchronous on `stream` (0 = null stream). Same bytes as any other
- * conforming producer for the same input and parameters. */
+ * conforming producer for the same input and parameters. Calls that overlap
+ * must use distinct workspaces. */
 gpulz_status gpulz_compress(const void* d_in, uint64_t nbytes, uint32_t symbol_bytes,
                             uint32_t chunk_symbols, uint32_t window, uint32_t min_match,
                             void* d_out, uint64_t out_capacity, uint64_t* d_out_bytes,
@@ -288,8 +297,9 @@ gpulz_status gpulz_huff_decompress(const void* d_in, uint64_t in_bytes, void* d_
 /* Kernel timing for benchmarks. While enabled, every gpulz_compress and
  * gpulz_decompress call records a pair of HIP events on its own stream
  * around each kernel it launches, so the times cover exactly those kernels.
- * Kernel ids: 0 chunk encode, 1 global scan + header, 2 record scatter,
- * 3 decode prepare (header check + table scan), 4 chunk decode, 5 a whole
+ * Kernel ids: 0 chunk encode (with the look-back and the record write-out),
+ * 1 compress preparation, 2 not used, 3 decode prepare (header check + table
+ * scan), 4 chunk decode, 5 a whole
  * gpulz_compress_batch call, 6 a whole gpulz_decompress_batch call, 7 a
  * whole gpulz_huff_compress call, 8 a whole gpulz_huff_decompress call.
  * gpulz_profile_enable(1) clears the accumulated times, (0) stops recording.

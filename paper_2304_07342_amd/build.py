@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB_PATH = os.path.join(PKG, "libgpulz.so")
-SOURCES = ["gpulz_api.hip", "lz_encode.hip", "lz_scan_scatter.hip", "lz_decode.hip", "lz_batch.hip",
+SOURCES = ["gpulz_api.hip", "lz_encode.hip", "lz_decode.hip", "lz_batch.hip",
            "huff.hip"]
 ARCH = os.environ.get("GPULZ_OFFLOAD_ARCH", "gfx950")
 

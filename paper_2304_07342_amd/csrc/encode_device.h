@@ -3,6 +3,7 @@
 #pragma once
 
 #include "gpulz_internal.h"
+#include "stream_device.h"
 #include "wave.h"
 
 namespace gpulz {
@@ -57,7 +58,17 @@ struct ChunkJob {
   uint32_t W, MIN;
   uint8_t* slot;        // scratch record: [flag area | payload]
   uint64_t flag_area;
-  uint32_t* sizes;      // receives {F, P}
+  uint32_t* sizes;      // receives {F, P} (two-pass path)
+  // single-pass path: the stream this chunk belongs to
+  uint64_t i, N;        // chunk index, chunks of the stream
+  uint64_t* desc;       // the stream's look-back descriptors
+  uint8_t* out;         // the stream
+  uint64_t capacity;
+  const uint8_t* in;    // the stream's input (the header's tail bytes)
+  uint64_t nbytes;
+  uint32_t S, policy;
+  uint64_t* out_bytes;  // written by the stream's last chunk
+  int32_t* status;
 };
 
 
@@ -432,10 +443,195 @@ __device__ __forceinline__ uint32_t search_token(const typename SymType<S>::T* w
   }
 }
 
-// Encodes one chunk into its scratch slot and writes {F, P} to job.sizes.
-// Every wave of the workgroup stages the chunk and builds the hit bitmap;
-// waves other than 0 return after that, wave 0 parses and encodes.
-template <int S, int WC>
+// ---- single-pass output: record offsets by decoupled look-back -------------
+//
+// A chunk's record offset is the sum of the record sizes before it (the
+// global prefix sum of section 3.2.2). Instead of a separate scan and a
+// compaction pass over scratch copies of the records (Kernels II and III of
+// section 3.3), each chunk publishes its size as soon as its parse ends, adds
+// up its predecessors' published sizes, and writes its table entry and
+// record once, at the final offset.
+
+__device__ __forceinline__ void desc_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t desc_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Polls of one look-back before it gives up (about half a second).
+constexpr uint32_t kLookbackPolls = 1u << 22;
+constexpr uint32_t kNoGroup = 0xFFFFFFFFu;
+
+// One wavefront, all lanes: publishes chunk i's record bytes `agg`, sums the
+// record bytes of chunks 0..i-1 from their descriptors, 64 per round, back to
+// the nearest inclusive prefix, publishes chunk i's inclusive prefix and
+// returns the exclusive one (the record's offset past the table). Chunk ids
+// follow the order of an atomic ticket taken when a workgroup starts, so
+// every predecessor belongs to a running or finished workgroup, which
+// publishes its size right after its own parse: every wait ends. As a guard
+// a wait of more than kLookbackPolls polls gives up; the chunk then
+// publishes and returns kDescValue ("failed"), and its successors pass it on.
+__device__ inline uint64_t lookback(uint64_t* desc, uint64_t i, uint64_t agg) {
+  const uint32_t lane = lane_id();
+  if (i == 0) {
+    if (lane == 0) desc_store(desc, kDescPrefix | agg);
+    return 0;
+  }
+  if (lane == 0) desc_store(desc + i, kDescAgg | agg);
+  uint64_t excl = 0;
+  uint64_t j = i;  // chunks [0, j) not yet summed
+  uint32_t polls = 0;
+  bool failed = false;
+  for (;;) {
+    // lane l reads chunk j - 1 - l; lanes past chunk 0 read an empty prefix
+    const uint64_t v = lane < j ? desc_load(desc + (j - 1 - lane)) : kDescPrefix;
+    const uint32_t st = (uint32_t)(v >> 62);
+    const uint64_t ready = ballot(st != 0);
+    const uint64_t pref = ballot(st == 2);
+    // lanes 0 .. run-1 are all published
+    const uint32_t run = ready == ~0ull ? 64u : (uint32_t)__builtin_ctzll(~ready);
+    const uint64_t pm = pref & (run == 64u ? ~0ull : ((1ull << run) - 1ull));
+    if (pm) {
+      const uint32_t pl = (uint32_t)__builtin_ctzll(pm);
+      // single-chunk sizes (lanes below pl) are far below 2^32 each
+      excl += readlane(wave_incl_scan(lane < pl ? (uint32_t)v : 0u), 63);
+      const uint64_t pv = ((uint64_t)readlane((uint32_t)(v >> 32), pl) << 32 |
+                           readlane((uint32_t)v, pl)) & kDescValue;
+      failed = pv == kDescValue;
+      excl += pv;
+      break;
+    }
+    if (run) {
+      excl += readlane(wave_incl_scan(lane < run ? (uint32_t)v : 0u), 63);
+      j -= run;
+      polls = 0;
+      continue;
+    }
+    if (++polls > kLookbackPolls) {
+      failed = true;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(4);
+  }
+  if (failed) excl = kDescValue;
+  if (lane == 0) desc_store(desc + i, kDescPrefix | (failed ? kDescValue : excl + agg));
+  return excl;
+}
+
+// The stream's last chunk, one wavefront after its look-back: the stream
+// size, the status (OK, OUT_OF_SPACE, or the internal error of a failed
+// look-back) and, if the stream fits, the header.
+__device__ inline void finish_stream(const ChunkJob& job, uint64_t excl, uint64_t agg) {
+  const uint32_t lane = lane_id();
+  if (excl == kDescValue) {
+    if (lane == 0) {
+      *job.out_bytes = 0;
+      *job.status = kInternal;
+    }
+    return;
+  }
+  const uint64_t total = kHeaderBytes + 8 * job.N + excl + agg;
+  const bool fits = total <= job.capacity;
+  if (lane == 0) {
+    *job.out_bytes = total;
+    *job.status = fits ? kOk : kOutOfSpace;
+  }
+  if (fits && lane < kHeaderBytes)
+    job.out[lane] = stream::header_byte(lane, job.nbytes, job.S, job.C, job.W, job.MIN, job.policy,
+                                        job.N, total, job.in);
+}
+
+// Parse-side handling of a finished group of up to 64 tokens. Two-pass
+// path: every group goes into the scratch slot. Single-pass path: groups
+// before the chunk's first pointer are all literals, whose payload is the
+// staged chunk itself, so nothing is written for them; from the first group
+// with a pointer (g0) on, groups go into the slot as before.
+template <int S, bool kSinglePass>
+__device__ __forceinline__ void emit_group(uint32_t cnt, uint32_t desc, uint32_t g,
+                                           const typename SymType<S>::T* win, uint8_t* slot,
+                                           uint64_t flag_area, uint32_t& pay, uint32_t& g0) {
+  if constexpr (kSinglePass) {
+    if (g0 == kNoGroup) {
+      if (ballot(lane_id() < cnt && (desc & 1u)) == 0) {
+        pay += S * cnt;
+        return;
+      }
+      g0 = g;
+      // flag words are copied out of the slot from an even group on, so
+      // that the copy starts 16-byte aligned: zero the one before an odd g0
+      if ((g & 1u) && lane_id() == 0) *reinterpret_cast<uint64_t*>(slot + 8u * (g - 1)) = 0;
+    }
+  }
+  encode_group<S>(cnt, desc, g, win, slot, flag_area, pay);
+}
+
+// One wavefront: the table entry and, if it ends within the capacity, the
+// record of chunk job.i at offset excl past the table. Flag bytes of groups
+// before g0 are zero and the rest come from the slot; payload bytes before
+// group g0 (64 S per group, all literals) come from the staged chunk in LDS,
+// the rest from the slot. No byte at or past the capacity is written.
+template <int S>
+__device__ inline void write_record(const ChunkJob& job, uint64_t excl, uint32_t F, uint32_t P,
+                                    uint32_t g0, const uint8_t* stage) {
+  const uint32_t lane = lane_id();
+  const uint64_t te = kHeaderBytes + 8 * job.i;
+  if (lane == 0 && te + 8 <= job.capacity)
+    *reinterpret_cast<uint64_t*>(job.out + te) = (uint64_t)F | ((uint64_t)P << 32);
+  const uint64_t base = kHeaderBytes + 8 * job.N;
+  if (excl == kDescValue || base + excl + F + P > job.capacity) return;
+  uint8_t* rec = job.out + base + excl;
+  if (g0 != kNoGroup) {
+    // the slot was written by this wavefront's lanes: complete those stores
+    // and drop any cached copy before reading it back
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  const uint64_t ge = 8ull * (g0 & ~1u);
+  const uint32_t fz = (uint32_t)min<uint64_t>(F, ge);
+  stream::fill_zero(rec, fz, lane, 64);
+  if (F > fz) stream::copy_bytes(rec + fz, job.slot + fz, F - fz, lane, 64);
+  const uint32_t pz = (uint32_t)min<uint64_t>(P, 64ull * S * g0);
+  stream::copy_bytes(rec + F, stage, pz, lane, 64);
+  if (P > pz) stream::copy_bytes(rec + F + pz, job.slot + job.flag_area + pz, P - pz, lane, 64);
+}
+
+// encode_group writing straight into the final record `rec` (F flag bytes,
+// then the payload): the group's flag bytes are stored one per lane, and only
+// those below F (the payload follows them).
+template <int S>
+__device__ __forceinline__ void encode_group_out(uint32_t cnt, uint32_t desc, uint32_t group,
+                                                 const typename SymType<S>::T* win, uint8_t* rec,
+                                                 uint32_t F, uint32_t pay) {
+  using T = typename SymType<S>::T;
+  const uint32_t lane = lane_id();
+  const bool valid = lane < cnt;
+  const bool is_ptr = valid && (desc & 1u);
+  const uint64_t pm = ballot(is_ptr);
+  const uint64_t lm = ballot(valid && !(desc & 1u));
+  const uint32_t off = pay + S * mbcnt(lm) + 2u * mbcnt(pm);
+  uint8_t* dst = rec + F + off;
+  if (is_ptr) {
+    dst[0] = (uint8_t)(desc >> 1);
+    dst[1] = (uint8_t)(desc >> 9);
+  } else if (valid) {
+    T v = win[desc >> 1];
+#pragma unroll
+    for (int b = 0; b < S; ++b) dst[b] = (uint8_t)((uint64_t)v >> (8 * b));
+  }
+  if (lane < 8 && 8u * group + lane < F) rec[8u * group + lane] = (uint8_t)(pm >> (8u * lane));
+}
+
+// Encodes one chunk. Every wave of the workgroup stages the chunk and builds
+// the hit bitmap; waves other than 0 return after that, wave 0 parses and
+// encodes.
+//   two-pass path (kSinglePass false): the record goes to the chunk's
+//     scratch slot and {F, P} to job.sizes, for a later scan and compaction;
+//   single-pass path: groups from the first pointer on go to the slot, then
+//     wave 0 takes the record offset from the look-back and writes the table
+//     entry and the record into the stream (and the header, size and status
+//     if this is the stream's last chunk).
+template <int S, int WC, bool kSinglePass = false>
 __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
   using T = typename SymType<S>::T;
   constexpr int V = Geo<S>::V;
@@ -486,20 +682,30 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
   for (int col = 0; col < WC; ++col) wmask[col] = ballot(64u * col + lane + 1u <= job.W);
 
   uint8_t* slot = job.slot;
-  uint32_t ntok = 0, pay = 0, desc = 0;
+  uint32_t ntok = 0, pay = 0, desc = 0, g0 = kNoGroup;
   uint32_t p = 0;
   CandCursor cc;
   cc.init(hits, nhw, sampled);
   while (p < c) {
     const uint32_t h = cc.next(p, c, hits, nhw, sampled);
-    // literals for [p, h)
+    // literals for [p, h); on the single-pass path, whole all-literal groups
+    // before the first pointer are only counted
+    if constexpr (kSinglePass) {
+      if (g0 == kNoGroup && (ntok & 63u) == 0 && h - p >= 64) {
+        const uint32_t k = (h - p) / 64;
+        ntok += 64 * k;
+        p += 64 * k;
+        pay += 64 * S * k;
+      }
+    }
     while (p < h) {
       const uint32_t sl = ntok & 63u;
       const uint32_t take = min(h - p, 64u - sl);
       if (lane >= sl && lane < sl + take) desc = (p + lane - sl) << 1;
       ntok += take;
       p += take;
-      if ((ntok & 63u) == 0) encode_group<S>(64, desc, (ntok >> 6) - 1, win, slot, job.flag_area, pay);
+      if ((ntok & 63u) == 0)
+        emit_group<S, kSinglePass>(64, desc, (ntok >> 6) - 1, win, slot, job.flag_area, pay, g0);
     }
     if (h >= c) break;
 
@@ -514,12 +720,21 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
     }
     if (lane == (ntok & 63u)) desc = val;
     ++ntok;
-    if ((ntok & 63u) == 0) encode_group<S>(64, desc, (ntok >> 6) - 1, win, slot, job.flag_area, pay);
+    if ((ntok & 63u) == 0)
+      emit_group<S, kSinglePass>(64, desc, (ntok >> 6) - 1, win, slot, job.flag_area, pay, g0);
   }
-  if (ntok & 63u) encode_group<S>(ntok & 63u, desc, ntok >> 6, win, slot, job.flag_area, pay);
-  if (lane == 0) {
-    job.sizes[0] = (ntok + 7) / 8;
-    job.sizes[1] = pay;
+  if (ntok & 63u)
+    emit_group<S, kSinglePass>(ntok & 63u, desc, ntok >> 6, win, slot, job.flag_area, pay, g0);
+  const uint32_t F = (ntok + 7) / 8;
+  if constexpr (kSinglePass) {
+    const uint64_t excl = lookback(job.desc, job.i, (uint64_t)F + pay);
+    if (job.i + 1 == job.N) finish_stream(job, excl, (uint64_t)F + pay);
+    write_record<S>(job, excl, F, pay, g0, stage);
+  } else {
+    if (lane == 0) {
+      job.sizes[0] = F;
+      job.sizes[1] = pay;
+    }
   }
 }
 
@@ -551,8 +766,8 @@ __device__ __forceinline__ void bits_range(uint32_t* bm, uint32_t a, uint32_t b,
   }
 }
 
-// Encodes one chunk like encode_chunk (the same stream), with the greedy
-// parse split across the workgroup's waves for latency: wave w parses its
+// Encodes one chunk like encode_chunk's single-pass path (the same stream),
+// with the greedy parse split across the workgroup's waves for latency: wave w parses its
 // segment [w seg, (w + 1) seg) as if a token started at its first position,
 // recording token starts, pointer starts and (L, d) per pointer. The greedy
 // parse is deterministic, so once the true parse reaches a position where a
@@ -561,9 +776,9 @@ __device__ __forceinline__ void bits_range(uint32_t* bm, uint32_t a, uint32_t b,
 // segment's starts, and wave 0 joins the segments: where the true parse leaves
 // a segment at that segment's own end, the extension is spliced in; otherwise
 // wave 0 walks the boundary token by token until the parses meet. Every wave
-// then encodes 64-token groups independently: a token's position comes from
-// prefix counts of the token bitmap, a group's payload offset from the
-// pointers before it.
+// then encodes 64-token groups independently, straight into the record at
+// the offset the look-back gives: a token's position comes from prefix counts
+// of the token bitmap, a group's payload offset from the pointers before it.
 template <int S, int WC>
 __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
   using T = typename SymType<S>::T;
@@ -746,6 +961,25 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
   }
   __syncthreads();
   const uint32_t ntok = pc_tok[nbw], nptr = pc_ptr[nbw];
+  const uint32_t F = (ntok + 7) / 8, P = S * (ntok - nptr) + 2 * nptr;
+  // ---- record offset (wave 0: look-back), then every wave writes its
+  // groups straight into the record (the join's `ends` words are free now)
+  if (wave == 0) {
+    const uint64_t excl = lookback(job.desc, job.i, (uint64_t)F + P);
+    if (job.i + 1 == job.N) finish_stream(job, excl, (uint64_t)F + P);
+    const uint64_t te = kHeaderBytes + 8 * job.i;
+    if (lane == 0) {
+      if (te + 8 <= job.capacity)
+        *reinterpret_cast<uint64_t*>(job.out + te) = (uint64_t)F | ((uint64_t)P << 32);
+      ends[0] = (uint32_t)excl;
+      ends[1] = (uint32_t)(excl >> 32);
+    }
+  }
+  __syncthreads();
+  const uint64_t excl = (uint64_t)ends[0] | ((uint64_t)ends[1] << 32);
+  const uint64_t rec_off = kHeaderBytes + 8 * job.N + excl;
+  if (excl == kDescValue || rec_off + F + P > job.capacity) return;
+  uint8_t* rec = job.out + rec_off;
   const uint32_t groups = (ntok + 63) / 64;
   for (uint32_t g = wave; g < groups; g += nwaves) {
     const uint32_t r = 64 * g + lane;  // this lane's token rank
@@ -779,12 +1013,8 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
     // first 64 g tokens
     const uint32_t p0 = readlane(p, 0);
     const uint32_t before_ptr = pc_ptr[p0 >> 5] + (uint32_t)__popc(ptr[p0 >> 5] & ((1u << (p0 & 31u)) - 1u));
-    uint32_t pay = S * (64 * g - before_ptr) + 2 * before_ptr;
-    encode_group<S>(min(64u, ntok - 64 * g), desc, g, win, job.slot, job.flag_area, pay);
-  }
-  if (tid == 0) {
-    job.sizes[0] = (ntok + 7) / 8;
-    job.sizes[1] = S * (ntok - nptr) + 2 * nptr;
+    const uint32_t pay = S * (64 * g - before_ptr) + 2 * before_ptr;
+    encode_group_out<S>(min(64u, ntok - 64 * g), desc, g, win, rec, F, pay);
   }
 }
 
@@ -860,34 +1090,44 @@ __device__ void encode_chunk_scan(const ChunkJob& job, uint8_t* lds) {
   if (wave != 0) return;
 
   // ---- greedy parse + encode (wave 0): candidates are exactly the
-  // positions whose walk found a run of at least MIN symbols
+  // positions whose walk found a run of at least MIN symbols; groups from the
+  // first pointer on go to the slot, then the record goes out at the offset
+  // the look-back gives (as encode_chunk's single-pass path)
   uint8_t* slot = job.slot;
-  uint32_t ntok = 0, pay = 0, desc = 0;
+  uint32_t ntok = 0, pay = 0, desc = 0, g0 = kNoGroup;
   uint32_t p = 0;
   CandCursor cc;
   cc.init(hits, nhw, false);
   while (p < c) {
     const uint32_t h = cc.next(p, c, hits, nhw, false);
+    if (g0 == kNoGroup && (ntok & 63u) == 0 && h - p >= 64) {
+      const uint32_t k = (h - p) / 64;
+      ntok += 64 * k;
+      p += 64 * k;
+      pay += 64 * S * k;
+    }
     while (p < h) {
       const uint32_t sl = ntok & 63u;
       const uint32_t take = min(h - p, 64u - sl);
       if (lane >= sl && lane < sl + take) desc = (p + lane - sl) << 1;
       ntok += take;
       p += take;
-      if ((ntok & 63u) == 0) encode_group<S>(64, desc, (ntok >> 6) - 1, win, slot, job.flag_area, pay);
+      if ((ntok & 63u) == 0)
+        emit_group<S, true>(64, desc, (ntok >> 6) - 1, win, slot, job.flag_area, pay, g0);
     }
     if (h >= c) break;
     const uint32_t L = Ltab[h], d = (uint32_t)Dtab[h] + 1u;
     if (lane == (ntok & 63u)) desc = 1u | (L << 1) | ((d & 0xFFu) << 9);
     ++ntok;
-    if ((ntok & 63u) == 0) encode_group<S>(64, desc, (ntok >> 6) - 1, win, slot, job.flag_area, pay);
+    if ((ntok & 63u) == 0)
+      emit_group<S, true>(64, desc, (ntok >> 6) - 1, win, slot, job.flag_area, pay, g0);
     p = h + L;
   }
-  if (ntok & 63u) encode_group<S>(ntok & 63u, desc, ntok >> 6, win, slot, job.flag_area, pay);
-  if (lane == 0) {
-    job.sizes[0] = (ntok + 7) / 8;
-    job.sizes[1] = pay;
-  }
+  if (ntok & 63u) emit_group<S, true>(ntok & 63u, desc, ntok >> 6, win, slot, job.flag_area, pay, g0);
+  const uint32_t F = (ntok + 7) / 8;
+  const uint64_t excl = lookback(job.desc, job.i, (uint64_t)F + pay);
+  if (job.i + 1 == job.N) finish_stream(job, excl, (uint64_t)F + pay);
+  write_record<S>(job, excl, F, pay, g0, stage);
 }
 
 template <int S, int WC>

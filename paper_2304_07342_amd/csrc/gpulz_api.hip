@@ -166,7 +166,7 @@ gpulz_status gpulz_compress_workspace_size(uint64_t nbytes, uint32_t S, uint32_t
                                            size_t* ws_bytes) {
   if (!ws_bytes || !valid_params(S, C, 1, 1)) return GPULZ_ERR_INVALID_ARG;
   // the slot size depends on min_match only for S == 1; size for the worst
-  *ws_bytes = (size_t)compress_workspace(num_chunks(nbytes, S, C), C, S, 1).total;
+  *ws_bytes = (size_t)fused_workspace(num_chunks(nbytes, S, C), C, S, 1).total;
   return GPULZ_OK;
 }
 
@@ -181,63 +181,49 @@ gpulz_status gpulz_compress_policy(const void* d_in, uint64_t nbytes, uint32_t S
   if ((uint64_t)C * S > kMaxChunkBytes) return GPULZ_ERR_UNSUPPORTED;
   if (policy == 1 && encode_scan_lds_bytes(C, S) > kMaxGroupLdsBytes) return GPULZ_ERR_UNSUPPORTED;
   const uint64_t N = num_chunks(nbytes, S, C);
-  const CompressWorkspace w = compress_workspace(N, C, S, 1);
+  if (N > (uint64_t)kMaxTickets * kMaxChunksPerLaunch) return GPULZ_ERR_UNSUPPORTED;
+  const FusedWorkspace w = fused_workspace(N, C, S, 1);
   if (!d_ws || ws_bytes < w.total) return GPULZ_ERR_WORKSPACE;
   uint8_t* ws = static_cast<uint8_t*>(d_ws);
   const SlotLayout sl = slot_layout(C, S, 1);
 
-  EncodeArgs e;
-  e.in = static_cast<const uint8_t*>(d_in);
-  e.nbytes = nbytes;
-  e.m = nbytes / S;
-  e.C = C;
-  e.W = W;
-  e.MIN = MIN;
-  e.slots = ws + w.slots_off;
-  e.slot_bytes = sl.slot_bytes;
-  e.flag_area = sl.flag_area;
-  e.sizes = reinterpret_cast<uint32_t*>(ws + w.sizes_off);
+  FusedArgs a;
+  a.in = static_cast<const uint8_t*>(d_in);
+  a.nbytes = nbytes;
+  a.m = nbytes / S;
+  a.N = N;
+  a.S = S;
+  a.C = C;
+  a.W = W;
+  a.MIN = MIN;
+  a.policy = policy;
+  a.out = static_cast<uint8_t*>(d_out);
+  a.capacity = out_capacity;
+  a.out_bytes = d_out_bytes;
+  a.status = d_status;
+  a.tickets = reinterpret_cast<uint64_t*>(ws);
+  a.desc = reinterpret_cast<uint64_t*>(ws + w.desc_off);
+  a.slots = ws + w.slots_off;
+  a.slot_bytes = sl.slot_bytes;
+  a.flag_area = sl.flag_area;
+  a.chunk0 = 0;
+  a.nchunks = 0;
+  a.launch = 0;
   uint32_t waves;
   {
     std::lock_guard<std::mutex> lk(g_defaults_mu);
     waves = g_defaults[width_index(S)].waves_per_chunk;
   }
-  int pi = prof_begin(0, stream);
-  const hipError_t le = policy == 0 ? launch_encode(e, S, N, waves, stream)
-                                    : launch_encode_scan(e, S, N, waves, stream);
-  if (le != hipSuccess) return GPULZ_ERR_HIP;
+  int pi = prof_begin(1, stream);
+  if (launch_fused_prep(a, stream) != hipSuccess) return GPULZ_ERR_HIP;
   prof_end(pi, stream);
-
-  ScanArgs sa;
-  sa.sizes = e.sizes;
-  sa.N = N;
-  sa.offsets = reinterpret_cast<uint64_t*>(ws + w.offsets_off);
-  sa.in = e.in;
-  sa.nbytes = nbytes;
-  sa.S = S;
-  sa.C = C;
-  sa.W = W;
-  sa.MIN = MIN;
-  sa.policy = policy;
-  sa.out = static_cast<uint8_t*>(d_out);
-  sa.capacity = out_capacity;
-  sa.out_bytes = d_out_bytes;
-  sa.status = d_status;
-  pi = prof_begin(1, stream);
-  if (launch_scan(sa, stream) != hipSuccess) return GPULZ_ERR_HIP;
-  prof_end(pi, stream);
-
-  ScatterArgs sc;
-  sc.sizes = e.sizes;
-  sc.offsets = sa.offsets;
-  sc.N = N;
-  sc.slots = e.slots;
-  sc.slot_bytes = sl.slot_bytes;
-  sc.flag_area = sl.flag_area;
-  sc.out = sa.out;
-  sc.capacity = out_capacity;
-  pi = prof_begin(2, stream);
-  if (launch_scatter(sc, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  pi = prof_begin(0, stream);
+  for (uint64_t c0 = 0; c0 < N; c0 += kMaxChunksPerLaunch) {
+    a.chunk0 = c0;
+    a.nchunks = N - c0 < kMaxChunksPerLaunch ? N - c0 : kMaxChunksPerLaunch;
+    if (launch_fused_encode(a, waves, stream) != hipSuccess) return GPULZ_ERR_HIP;
+    ++a.launch;
+  }
   prof_end(pi, stream);
   return GPULZ_OK;
 }

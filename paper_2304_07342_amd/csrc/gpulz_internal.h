@@ -17,7 +17,10 @@ constexpr uint32_t kDecodeRingBytes = 16 * 1024;
 constexpr uint64_t kMaxGroupLdsBytes = 64 * 1024;  // LDS one workgroup may allocate
 
 // Device status values (same numbering as gpulz_status).
-enum : int32_t { kOk = 0, kInvalidArg = 1, kOutOfSpace = 2, kCorrupt = 3, kWorkspace = 4 };
+enum : int32_t {
+  kOk = 0, kInvalidArg = 1, kOutOfSpace = 2, kCorrupt = 3, kWorkspace = 4,
+  kInternal = 5  // a bounded device-side wait gave up (reported as GPULZ_ERR_HIP)
+};
 
 __host__ __device__ constexpr uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
@@ -37,64 +40,65 @@ __host__ __device__ inline SlotLayout slot_layout(uint32_t C, uint32_t S, uint32
   return l;
 }
 
-// Workspace = sizes[N] (u32 F, u32 P) | offsets[N+1] (u64) | slots[N].
-struct CompressWorkspace {
-  uint64_t sizes_off, offsets_off, slots_off, total;
+// ---- single-pass compress: records written once at their final offset ----
+//
+// Chunk ids come from an atomic ticket in the order workgroups start, and
+// every chunk publishes its record size in a look-back descriptor
+// (u64: state in bits 62-63, value in bits 0-61). State 1: the value is this
+// chunk's record bytes; state 2: the record bytes of chunks 0..i (inclusive
+// prefix). A chunk sums its predecessors' values back to the nearest
+// inclusive prefix, so its record offset needs no separate scan pass.
+constexpr uint64_t kDescAgg = 1ull << 62;
+constexpr uint64_t kDescPrefix = 2ull << 62;
+constexpr uint64_t kDescValue = (1ull << 62) - 1;  // also the "failed" prefix value
+// Blocks per launch of the chunk encoders (launches of more chunks are
+// split; every work-item count then stays far below 2^32).
+constexpr uint64_t kMaxChunksPerLaunch = 1ull << 22;
+
+// Workspace = ctrl (256 B: one ticket per launch) | desc[N] (u64) | slots[N].
+// A slot only receives a chunk's 64-token groups from its first pointer on;
+// all-literal groups before it are copied from the staged chunk.
+constexpr uint32_t kMaxTickets = 32;
+struct FusedWorkspace {
+  uint64_t desc_off, slots_off, total;
 };
 
-__host__ __device__ inline CompressWorkspace compress_workspace(uint64_t N, uint32_t C, uint32_t S,
-                                                                uint32_t min_match) {
-  CompressWorkspace w;
-  w.sizes_off = 0;
-  w.offsets_off = align_up(8 * N, 256);
-  w.slots_off = w.offsets_off + align_up(8 * (N + 1), 256);
+__host__ __device__ inline FusedWorkspace fused_workspace(uint64_t N, uint32_t C, uint32_t S,
+                                                          uint32_t min_match) {
+  FusedWorkspace w;
+  w.desc_off = 256;
+  w.slots_off = w.desc_off + align_up(8 * N, 256);
   w.total = w.slots_off + N * slot_layout(C, S, min_match).slot_bytes + 256;
   return w;
 }
 
-struct EncodeArgs {
+struct FusedArgs {
   const uint8_t* in;
-  uint64_t nbytes;      // input bytes (for bounds of the staging loads)
-  uint64_t m;           // input symbols
-  uint32_t C, W, MIN;
-  uint8_t* slots;
-  uint64_t slot_bytes;
-  uint64_t flag_area;
-  uint32_t* sizes;      // 2 per chunk: F, P
-};
-
-struct ScanArgs {
-  const uint32_t* sizes;
-  uint64_t N;
-  uint64_t* offsets;    // N + 1 entries (exclusive prefix, then the sum)
-  const uint8_t* in;    // for the tail bytes
-  uint64_t nbytes;
+  uint64_t nbytes, m, N;
   uint32_t S, C, W, MIN, policy;
   uint8_t* out;
   uint64_t capacity;
   uint64_t* out_bytes;
   int32_t* status;
+  uint64_t* tickets;   // kMaxTickets counters, one per launch
+  uint64_t* desc;      // N look-back descriptors
+  uint8_t* slots;
+  uint64_t slot_bytes, flag_area;
+  uint64_t chunk0;     // first chunk of this launch
+  uint64_t nchunks;    // chunks of this launch
+  uint32_t launch;     // index of this launch (its ticket)
 };
 
-struct ScatterArgs {
-  const uint32_t* sizes;
-  const uint64_t* offsets;
-  uint64_t N;
-  const uint8_t* slots;
-  uint64_t slot_bytes;
-  uint64_t flag_area;
-  uint8_t* out;
-  uint64_t capacity;
-};
+// Zeroes the descriptors and tickets; for N = 0 also writes the header, size
+// and status (one small kernel).
+hipError_t launch_fused_prep(const FusedArgs& a, hipStream_t s);
+// Encodes chunks [a.chunk0, a.chunk0 + a.nchunks) (at most
+// kMaxChunksPerLaunch) with ticket a.launch, for match policy a.policy.
+hipError_t launch_fused_encode(const FusedArgs& a, uint32_t waves, hipStream_t s);
 
-// Launchers (asynchronous; return the launch's hipError_t).
-hipError_t launch_encode(const EncodeArgs& a, uint32_t S, uint64_t N, uint32_t waves, hipStream_t s);
-hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
-hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
+
 size_t encode_lds_bytes(uint32_t C, uint32_t S, uint32_t W);
 size_t encode_scan_lds_bytes(uint32_t C, uint32_t S);
-hipError_t launch_encode_scan(const EncodeArgs& a, uint32_t S, uint64_t N, uint32_t waves,
-                              hipStream_t s);
 
 // ---- decompress -------------------------------------------------------------
 

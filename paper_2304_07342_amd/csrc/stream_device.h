@@ -78,6 +78,19 @@ __device__ inline void copy_bytes(uint8_t* dst, const uint8_t* src, uint32_t len
   for (uint32_t b = head + 16 * nw + tid; b < len; b += nthreads) dst[b] = src[b];
 }
 
+// Writes len zero bytes at any destination: bytes up to the first 16-byte
+// boundary, aligned 16-byte words, then the last bytes (the edges never touch
+// a neighbour's bytes).
+__device__ inline void fill_zero(uint8_t* dst, uint64_t len, uint32_t tid, uint32_t nthreads) {
+  uint64_t head = (16u - ((uintptr_t)dst & 15u)) & 15u;
+  if (head > len) head = len;
+  for (uint64_t b = tid; b < head; b += nthreads) dst[b] = 0;
+  const uint64_t nw = (len - head) / 16;
+  uint4* d4 = reinterpret_cast<uint4*>(dst + head);
+  for (uint64_t k = tid; k < nw; k += nthreads) d4[k] = make_uint4(0u, 0u, 0u, 0u);
+  for (uint64_t b = head + 16 * nw + tid; b < len; b += nthreads) dst[b] = 0;
+}
+
 // Workgroup-wide exclusive scan of F_i + P_i over N chunks (sizes holds
 // {F, P} pairs) into offs; returns the total. blockDim is a multiple of 64;
 // `scratch` holds blockDim/64 + 1 u64.

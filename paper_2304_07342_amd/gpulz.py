@@ -32,7 +32,7 @@ EXPORTS = (
     "gpulz_profile_read", "gpulz_huff_compress_bound", "gpulz_huff_compress_workspace_size",
     "gpulz_huff_compress", "gpulz_huff_decompress_workspace_size", "gpulz_huff_decompress",
 )
-KERNEL_NAMES = ("encode", "scan", "scatter", "decode_prepare", "decode", "compress_batch",
+KERNEL_NAMES = ("encode", "prep", "unused", "decode_prepare", "decode", "compress_batch",
                 "decompress_batch", "huff_compress", "huff_decompress")
 
 

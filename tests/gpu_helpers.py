@@ -20,7 +20,8 @@ def to_device(x: np.ndarray):
 def gpu_compress(x, S, C, W, MIN, capacity=None, slack=64, policy=0):
     """Run gpulz_compress; returns (status, stream bytes or None, out_bytes,
     canary_intact). The output buffer has `slack` canary bytes past the
-    capacity to detect writes beyond it."""
+    capacity to detect writes beyond it (on OUT_OF_SPACE too: no byte at or
+    past the capacity may be written)."""
     import torch
     b = np.ascontiguousarray(x).view(np.uint8).reshape(-1) if isinstance(x, np.ndarray) else \
         np.frombuffer(bytes(x), dtype=np.uint8)
@@ -49,8 +50,7 @@ def gpu_compress(x, S, C, W, MIN, capacity=None, slack=64, policy=0):
     canary_ok = bool((host[cap:] == CANARY).all())
     if status == gpulz.GPULZ_OK:
         return status, host[:out_bytes].tobytes(), out_bytes, canary_ok
-    untouched = bool((host == CANARY).all())
-    return status, None, out_bytes, canary_ok and untouched
+    return status, None, out_bytes, canary_ok
 
 
 def gpu_decompress(stream: bytes, capacity: int, slack=64):

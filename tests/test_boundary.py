@@ -114,6 +114,13 @@ def test_compress_rejects_misaligned_and_null_pointers():
     assert args
 
 
+def test_compress_rejects_more_chunks_than_tickets():
+    # 2^27 + 1 chunks (S = 1, C = 1): refused before any launch
+    st = gpulz.gpulz_compress(FAKE, (1 << 27) + 1, 1, 1, 16, 2, FAKE, 1 << 20, FAKE, FAKE, FAKE,
+                              1 << 62)
+    assert st == gpulz.GPULZ_ERR_UNSUPPORTED
+
+
 def test_compress_rejects_small_workspace():
     need = gpulz.gpulz_compress_workspace_size(4096, 2, 64)
     st = gpulz.gpulz_compress(FAKE, 4096, 2, 64, 16, 2, FAKE, 1 << 20, FAKE, FAKE, FAKE, need - 1)

@@ -129,14 +129,23 @@ def test_tiny_and_ragged(n, S):
     assert st == gpulz.GPULZ_OK and d == x.tobytes()
 
 
-def test_compress_out_of_space_writes_nothing():
-    x = synth.mixed(50000, 2, seed=5)
-    ref = oracle.compress(x, 2, 512, 128, 2)
-    _say("out of space")
-    st, s, need, untouched = gpu_compress(x, 2, 512, 128, 2, capacity=len(ref) - 1)
-    assert st == gpulz.GPULZ_ERR_OUT_OF_SPACE and need == len(ref) and untouched
-    st, s, need, canary = gpu_compress(x, 2, 512, 128, 2, capacity=len(ref))
+# OUT_OF_SPACE: the required size is reported and no byte at or past the
+# capacity is written, for capacities from the header alone up to one byte
+# short, on both encoders (split parse with few chunks, per-chunk otherwise),
+# and for an input of no chunk at all.
+@pytest.mark.parametrize("n,C", [(50000, 512), (600000, 256)])
+def test_compress_out_of_space_writes_nothing_past_capacity(n, C):
+    x = synth.mixed(n, 2, seed=5)
+    ref = oracle.compress(x, 2, C, 128, 2)
+    N = -(-(n // 2) // C)
+    for cap in (0, 63, 64, 64 + 8 * N - 1, 64 + 8 * N + 100, len(ref) // 2, len(ref) - 1):
+        _say("out of space", n, C, cap)
+        st, s, need, canary = gpu_compress(x, 2, C, 128, 2, capacity=cap)
+        assert st == gpulz.GPULZ_ERR_OUT_OF_SPACE and need == len(ref) and canary, cap
+    st, s, need, canary = gpu_compress(x, 2, C, 128, 2, capacity=len(ref))
     assert st == gpulz.GPULZ_OK and s == ref and canary
+    st, s, need, canary = gpu_compress(x[:1], 2, C, 128, 2, capacity=63)
+    assert st == gpulz.GPULZ_ERR_OUT_OF_SPACE and need == 64 and canary
 
 
 def test_decompress_out_of_space():
