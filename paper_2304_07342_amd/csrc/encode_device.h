@@ -2,6 +2,8 @@
 // the persistent batch kernel.
 #pragma once
 
+#include <type_traits>
+
 #include "gpulz_internal.h"
 #include "stream_device.h"
 #include "wave.h"
@@ -77,10 +79,22 @@ template <int S> struct Geo {
   static constexpr uint32_t kBlock = 64u * V;       // positions per wave block
 };
 
+// Window columns of the streaming search (1- and 2-byte symbols): 4 / S
+// offsets per lane, so one column of 64 lanes covers 256 / S offsets.
+__host__ __device__ constexpr uint32_t stream_cols(uint32_t S, uint32_t wc) {
+  return S == 1 ? 1u : (S == 2 ? (wc <= 2 ? 1u : 2u) : 0u);
+}
+// Bytes before the staged chunk: window reads reach 64 WC S bytes back (the
+// per-column searches) or 256 bytes per streaming column.
+__host__ __device__ constexpr uint32_t pad_for(uint32_t S, uint32_t wc) {
+  const uint32_t a = 64u * wc * S, b = 256u * stream_cols(S, wc);
+  return (uint32_t)align_up((a > b ? a : b) + 16u, 16);
+}
+
 // LDS layout: [pad | chunk (rounded up to whole 1 KiB blocks) + slack | hit bitmap]
 template <int S, int WC>
 __host__ __device__ constexpr uint32_t pad_bytes() {
-  return (uint32_t)align_up(64u * WC * S + 16u, 16);
+  return pad_for(S, WC);
 }
 __host__ __device__ constexpr uint64_t chunk_lds_bytes(uint32_t C, uint32_t S) {
   return align_up((uint64_t)C * S, 1024) + 64;
@@ -90,7 +104,7 @@ __host__ __device__ constexpr uint64_t hit_words(uint32_t C, uint32_t S) {
 }
 // LDS of one chunk encoder with wc window columns.
 __host__ __device__ constexpr uint64_t encode_lds(uint32_t C, uint32_t S, uint32_t wc) {
-  return align_up(64ull * wc * S + 16, 16) + chunk_lds_bytes(C, S) + 4 * hit_words(C, S);
+  return pad_for(S, wc) + chunk_lds_bytes(C, S) + 4 * hit_words(C, S);
 }
 
 template <int S>
@@ -443,6 +457,471 @@ __device__ __forceinline__ uint32_t search_token(const typename SymType<S>::T* w
   }
 }
 
+// ---- streaming exact search for 1- and 2-byte symbols ----------------------
+//
+// The greedy parse asks for the longest match at each token start h. For
+// 1- and 2-byte symbols the window offsets are packed K = 4 / S to a lane:
+// lane l of column c holds offsets d = 64 K c + K l + K - k in its k-th byte
+// (S = 1) or half (S = 2), so that the dword ending just before position q
+// holds sym[q - d] for all of them (kept in registers, see StreamMatch). A
+// position q is compared with its whole window at once: the dword of K
+// copies of sym[q] XOR each lane's dword, reduced to one "differs" bit per
+// offset (a
+// byte-wise carry trick for bytes, a packed 16-bit minimum with 1 for
+// halves). The offsets whose match at h is at least t symbols long are a
+// live bit set: start with the offsets d <= min(W, h) that match at h, and
+// clear the differing ones at h + 1, h + 2, ... until none is left or the
+// length limit is reached. The token's length is the number of positions
+// passed and its offset the largest survivor of the last position before
+// the set emptied (ties go to the largest offset).
+//
+// Every position is compared once: the position where a match ends is the
+// next token's start (greedy parse), so its differs bits are kept and
+// reused. Only a rewind (a literal after a partial match with MIN >= 3, or
+// the capped fallback below) or a jump over non-candidates reloads.
+//
+// The live set ignores the cap L <= d (a match never overlaps its own
+// source) while it runs. If the largest survivor d has d >= L the uncapped
+// result is also the capped one (it reaches length L and no offset can give
+// more). Otherwise (periodic runs shorter than their length, e.g. constant
+// runs) the token is recomputed by the per-column search with the cap.
+
+template <int S> struct Pack {
+  static constexpr uint32_t K = 4 / S;         // offsets per lane
+  static constexpr uint32_t kPerCol = 64 * K;  // offsets per column
+  // one bit per offset: bit 7 of each byte / bit 0 of each half
+  static constexpr uint32_t kLive = S == 1 ? 0x80808080u : 0x00010001u;
+};
+
+constexpr uint32_t kNeedCapped = 1;  // token(): recompute with the L <= d cap
+
+// Differs bits of K window symbols y against K copies xr of sym[q].
+template <int S>
+__device__ __forceinline__ uint32_t differs(uint32_t y, uint32_t xr) {
+  const uint32_t e = y ^ xr;
+  if constexpr (S == 1) {
+    // bit 7 of a byte: it is nonzero (low 7 bits via a carry into bit 7,
+    // which never crosses into the next byte, or bit 7 itself)
+    return ((e & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | e;
+  } else {
+    uint32_t z;
+    // each half: min(e, 1), i.e. 1 iff the two symbols differ
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(z) : "v"(e), "s"(0x00010001u));
+    return z;
+  }
+}
+
+// One whole-wave shift: lane l takes src of lane l - 1, lane 0 takes `fill`.
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t src, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)src, 0x138, 0xF, 0xF, false);
+}
+
+template <int S, int NC>
+struct StreamMatch {
+  using P = Pack<S>;
+  // Window registers for position q, with qa = (S q) & ~3 the byte address
+  // of the dword holding q's first byte: lane l of column c holds in A[c]
+  // the dword at qa - 4 (64 c + l + 1) and in B[c] the one after it, so
+  // alignbyte(B, A, (S q) & 3) is the dword ending just before q's first
+  // byte, whose parts are sym[q - d] for the lane's offsets. When q moves
+  // into the next dword, A takes B and B shifts up one lane (lane 0 of
+  // column 0 takes the dword at qa + 4, lane 0 of a higher column the old
+  // lane 63 of the column below): no LDS read per position.
+  const uint32_t* stage;
+  uint32_t wmask[NC];  // live bits of the offsets d <= W
+  uint32_t q;          // next position to compare
+  uint32_t sh;         // (S q) & 3
+  uint32_t A[NC], B[NC];
+  uint32_t xc, xn;     // the dwords at qa and qa + 4 (same in all lanes)
+  uint32_t z[NC];      // differs bits of position q - 1
+
+  // Live bits of column c for the offsets d <= lim.
+  __device__ __forceinline__ static uint32_t mask_le(uint32_t c, uint32_t lim, uint32_t lane) {
+    const int32_t dmax = (int32_t)(c * P::kPerCol + P::K * lane + P::K);  // offset of part 0
+    const int32_t t = dmax - (int32_t)lim;  // parts k < t hold offsets above lim
+    if (t <= 0) return P::kLive;
+    if (t >= (int32_t)P::K) return 0u;
+    return P::kLive << (8 * S * t);
+  }
+
+  __device__ __forceinline__ void init(const uint8_t* st, uint32_t W, uint32_t lane) {
+    stage = reinterpret_cast<const uint32_t*>(st);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) wmask[c] = mask_le(c, W, lane);
+    q = ~0u;
+  }
+
+  // Window registers for position pos (aligned dword reads; the pad before
+  // the chunk holds the 256 NC bytes the highest offsets reach back).
+  __device__ __forceinline__ void seek(uint32_t pos, uint32_t lane) {
+    q = pos;
+    sh = (S * pos) & 3u;
+    const uint32_t* w = stage + (S * pos) / 4;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      A[c] = w[-(int32_t)(64 * c + lane + 1)];
+      B[c] = w[-(int32_t)(64 * c + lane)];
+    }
+    xc = w[0];
+    xn = w[1];
+  }
+
+  // Differs bits of position q; then q + 1.
+  __device__ __forceinline__ void step() {
+    const uint32_t sel = sh * 0x01010101u + (S == 1 ? 0u : 0x01000100u);
+    const uint32_t xr = __builtin_amdgcn_perm(xc, xc, sel);  // K copies of sym[q]
+#pragma unroll
+    for (int c = 0; c < NC; ++c) z[c] = differs<S>(__builtin_amdgcn_alignbyte(B[c], A[c], sh), xr);
+    ++q;
+    sh += S;
+    if (sh == 4) {
+      sh = 0;
+#pragma unroll
+      for (int c = NC - 1; c >= 1; --c) {
+        const uint32_t carry = readlane(B[c - 1], 63);
+        A[c] = B[c];
+        B[c] = wave_shr1(B[c], carry);
+      }
+      A[0] = B[0];
+      B[0] = wave_shr1(B[0], xn);
+      xc = xn;
+      xn = stage[(S * q) / 4 + 1];  // stays within the slack after the chunk
+    }
+  }
+
+  __device__ __forceinline__ static bool any(const uint32_t (&v)[NC]) {
+    uint32_t o = v[0];
+#pragma unroll
+    for (int c = 1; c < NC; ++c) o |= v[c];
+    return ballot(o != 0) != 0;
+  }
+
+  // Largest offset with a live bit.
+  __device__ __forceinline__ static uint32_t largest(const uint32_t (&v)[NC]) {
+#pragma unroll
+    for (int c = NC - 1; c >= 0; --c) {
+      const uint64_t b = ballot(v[c] != 0);
+      if (b) {
+        const uint32_t l = 63u - (uint32_t)__builtin_clzll(b);
+        const uint32_t k = (uint32_t)__builtin_ctz(readlane(v[c], l)) / (8 * S);
+        return c * P::kPerCol + P::K * l + P::K - k;
+      }
+    }
+    return 0;
+  }
+
+  // The token at chunk position h < c, lim = min(255, c - h): L << 9 | d
+  // for a match of at least MIN symbols, 0 for a literal, kNeedCapped if
+  // the cap L <= d decides it. All lanes; the result is wave-uniform.
+  __device__ __forceinline__ uint32_t token(uint32_t h, uint32_t lim, uint32_t W, uint32_t MIN,
+                                            uint32_t lane) {
+    if (h + 1 != q) {  // z does not hold position h yet
+      if (h != q) seek(h, lane);
+      step();
+    }
+    uint32_t live[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      live[c] = (h >= W ? wmask[c] : (wmask[c] & mask_le(c, h, lane))) & ~z[c];
+    if (!any(live)) return 0u;
+    uint32_t t = 1;  // live: the offsets whose match at h is at least t long
+    while (t < lim) {
+      step();
+      uint32_t nl[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) nl[c] = live[c] & ~z[c];
+      if (!any(nl)) break;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) live[c] = nl[c];
+      ++t;
+    }
+    if (t < MIN) return 0u;
+    const uint32_t d = largest(live);
+    if (d < t) return kNeedCapped;
+    return t << 9 | d;
+  }
+};
+
+template <int S> constexpr bool kStreamSearch = S <= 2;
+template <int S, int WC>
+using StreamMatchFor = StreamMatch<S, (stream_cols(S, WC) ? (int)stream_cols(S, WC) : 1)>;
+
+// The exact longest match at h through the streaming search (1- and 2-byte
+// symbols, with the capped per-column search as its fallback) or the
+// per-column search alone.
+template <int S, int WC>
+__device__ __forceinline__ uint32_t find_token(StreamMatchFor<S, WC>& sm,
+                                               const typename SymType<S>::T* win, uint32_t h,
+                                               uint32_t c, uint32_t W, uint32_t MIN,
+                                               const uint64_t (&wmask)[WC], uint32_t lane) {
+  if constexpr (kStreamSearch<S>) {
+    const uint32_t key = sm.token(h, min(kMaxMatch, c - h), W, MIN, lane);
+    if (key != kNeedCapped) return key;
+  }
+  return search_token<S, WC>(win, h, c, W, MIN, wmask, lane);
+}
+
+// The inner loop of the dense parse for one window column (1-byte symbols
+// with W <= 256, 2-byte ones with W <= 128), written out: it extends an open
+// token position by position until no offset matches or n reaches steps.
+// In: live (the token's live bits), n (positions matched past the first),
+// steps, qa (LDS byte address of the dword holding the next position), ph
+// (that position's byte within the dword), wbase (this lane's window dword
+// offset from the compared position's dword). Out: live, n (unchanged
+// meaning), z (differs bits of the last compared position, valid if the
+// token died, i.e. n < steps). The dword group's kK positions are unrolled
+// with constant shifts and selectors; the loads complete inside the block.
+template <int S>
+__device__ __forceinline__ void extend_run(uint32_t& live, uint32_t& n, uint32_t& z, uint32_t steps,
+                                           uint32_t qa, uint32_t ph, uint32_t wbase) {
+  uint32_t a, b, x, t0, t1, wa, xa;
+  if constexpr (S == 1) {
+    const uint32_t s1 = 0x01010101u, s2 = 0x02020202u, s3 = 0x03030303u;
+#define GPULZ_STEP1(K, SEL)                                   \
+  "s_cmp_eq_u32 %[n], %[steps]\n\t"                           \
+  "s_cbranch_scc1 .Lend%=\n\t"                                \
+  "v_perm_b32 %[t0], %[x], %[x], " SEL "\n\t"                 \
+  "v_alignbyte_b32 %[t1], %[b], %[a], " #K "\n\t"             \
+  "v_xor_b32 %[t1], %[t1], %[t0]\n\t"                         \
+  "v_and_b32 %[t0], 0x7f7f7f7f, %[t1]\n\t"                    \
+  "v_add_u32 %[t0], 0x7f7f7f7f, %[t0]\n\t"                    \
+  "v_or_b32 %[z], %[t0], %[t1]\n\t"                           \
+  "v_bfi_b32 %[t0], %[z], 0, %[live]\n\t"                     \
+  "v_cmp_ne_u32 vcc, 0, %[t0]\n\t"                            \
+  "s_cbranch_vccz .Lend%=\n\t"                                \
+  "v_mov_b32 %[live], %[t0]\n\t"                              \
+  "s_add_u32 %[n], %[n], 1\n\t"
+    asm volatile(
+        "v_add_u32 %[wa], %[qa], %[wbase]\n\t"
+        "v_mov_b32 %[xa], %[qa]\n\t"
+        "ds_read_b32 %[a], %[wa]\n\t"
+        "ds_read_b32 %[b], %[wa] offset:4\n\t"
+        "ds_read_b32 %[x], %[xa]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_cmp_eq_u32 %[ph], 1\n\t"
+        "s_cbranch_scc1 .Lp1%=\n\t"
+        "s_cmp_eq_u32 %[ph], 2\n\t"
+        "s_cbranch_scc1 .Lp2%=\n\t"
+        "s_cmp_eq_u32 %[ph], 3\n\t"
+        "s_cbranch_scc1 .Lp3%=\n"
+        ".Lp0%=:\n\t"
+        GPULZ_STEP1(0, "0")
+        "\n.Lp1%=:\n\t"
+        GPULZ_STEP1(1, "%[s1]")
+        "\n.Lp2%=:\n\t"
+        GPULZ_STEP1(2, "%[s2]")
+        "\n.Lp3%=:\n\t"
+        GPULZ_STEP1(3, "%[s3]")
+        "v_add_u32 %[wa], 4, %[wa]\n\t"
+        "v_add_u32 %[xa], 4, %[xa]\n\t"
+        "ds_read_b32 %[a], %[wa]\n\t"
+        "ds_read_b32 %[b], %[wa] offset:4\n\t"
+        "ds_read_b32 %[x], %[xa]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_branch .Lp0%=\n"
+        ".Lend%=:"
+        : [live] "+v"(live), [n] "+s"(n), [z] "=&v"(z), [a] "=&v"(a), [b] "=&v"(b), [x] "=&v"(x),
+          [t0] "=&v"(t0), [t1] "=&v"(t1), [wa] "=&v"(wa), [xa] "=&v"(xa)
+        : [steps] "s"(steps), [qa] "s"(qa), [ph] "s"(ph), [wbase] "v"(wbase), [s1] "s"(s1),
+          [s2] "s"(s2), [s3] "s"(s3)
+        : "vcc", "scc", "memory");
+#undef GPULZ_STEP1
+  } else {
+    const uint32_t s0 = 0x01000100u, s2 = 0x03020302u, ones = 0x00010001u;
+#define GPULZ_STEP2(K, SEL)                                   \
+  "s_cmp_eq_u32 %[n], %[steps]\n\t"                           \
+  "s_cbranch_scc1 .Lend%=\n\t"                                \
+  "v_perm_b32 %[t0], %[x], %[x], " SEL "\n\t"                 \
+  "v_alignbyte_b32 %[t1], %[b], %[a], " #K "\n\t"             \
+  "v_xor_b32 %[t1], %[t1], %[t0]\n\t"                         \
+  "v_pk_min_u16 %[z], %[t1], %[ones]\n\t"                     \
+  "v_bfi_b32 %[t0], %[z], 0, %[live]\n\t"                     \
+  "v_cmp_ne_u32 vcc, 0, %[t0]\n\t"                            \
+  "s_cbranch_vccz .Lend%=\n\t"                                \
+  "v_mov_b32 %[live], %[t0]\n\t"                              \
+  "s_add_u32 %[n], %[n], 1\n\t"
+    asm volatile(
+        "v_add_u32 %[wa], %[qa], %[wbase]\n\t"
+        "v_mov_b32 %[xa], %[qa]\n\t"
+        "ds_read_b32 %[a], %[wa]\n\t"
+        "ds_read_b32 %[b], %[wa] offset:4\n\t"
+        "ds_read_b32 %[x], %[xa]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_cmp_eq_u32 %[ph], 2\n\t"
+        "s_cbranch_scc1 .Lp2%=\n"
+        ".Lp0%=:\n\t"
+        GPULZ_STEP2(0, "%[s0]")
+        "\n.Lp2%=:\n\t"
+        GPULZ_STEP2(2, "%[s2]")
+        "v_add_u32 %[wa], 4, %[wa]\n\t"
+        "v_add_u32 %[xa], 4, %[xa]\n\t"
+        "ds_read_b32 %[a], %[wa]\n\t"
+        "ds_read_b32 %[b], %[wa] offset:4\n\t"
+        "ds_read_b32 %[x], %[xa]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_branch .Lp0%=\n"
+        ".Lend%=:"
+        : [live] "+v"(live), [n] "+s"(n), [z] "=&v"(z), [a] "=&v"(a), [b] "=&v"(b), [x] "=&v"(x),
+          [t0] "=&v"(t0), [t1] "=&v"(t1), [wa] "=&v"(wa), [xa] "=&v"(xa)
+        : [steps] "s"(steps), [qa] "s"(qa), [ph] "s"(ph), [wbase] "v"(wbase), [s0] "s"(s0),
+          [s2] "s"(s2), [ones] "s"(ones)
+        : "vcc", "scc", "memory");
+#undef GPULZ_STEP2
+  }
+}
+
+// Greedy parse of a whole dense chunk [0, c) (1- and 2-byte symbols,
+// MIN <= 2), every position compared once with its window (StreamMatch's
+// packed layout). A token open at h with t positions matched either
+// survives position h + t (some offset still matches), or ends there: a
+// pointer (t, largest survivor) if t >= MIN, else a literal at h; either
+// way the next token starts at h + t (MIN <= 2), whose compare is the one
+// just made. A token also ends at min(255, c - h) positions. A token that
+// the cap L <= d decides (see StreamMatch) is redone by the capped
+// per-column search, and the parse continues from its end. Each compare
+// reads its window dwords from LDS at dword alignment.
+//
+// Token descriptors are collected one per lane in dlo; flush(dlo) takes
+// each full group of 64. Returns the number of tokens left in dlo.
+template <int S, int WC, typename Flush>
+__device__ __forceinline__ uint32_t parse_dense(const uint8_t* stage, uint32_t c, uint32_t W,
+                                                uint32_t MIN, const uint64_t (&wmask64)[WC],
+                                                uint32_t lane, uint32_t& dlo, Flush&& flush) {
+  using T = typename SymType<S>::T;
+  using SM = StreamMatchFor<S, WC>;
+  constexpr int NC = stream_cols(S, WC);
+  const T* win = reinterpret_cast<const T*>(stage);
+  const uint32_t* st = reinterpret_cast<const uint32_t*>(stage);
+  uint32_t wm[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) wm[k] = SM::mask_le(k, W, lane);
+
+  uint32_t nb = 0, lo = dlo;
+  // Per-lane byte offsets (from the stage) of the window dwords of column j,
+  // relative to the dword of the compared position.
+  int32_t woff[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) woff[j] = -4 * (int32_t)(64 * j + lane + 1);
+  // z = differs bits of position vq, a copy of the position in a vector
+  // register: its address and shift arithmetic run on the vector unit, which
+  // has issue slots to spare, instead of the scalar unit, which the parse's
+  // control flow keeps busy.
+#define GPULZ_DENSE_COMPARE(vq)                                                            \
+  do {                                                                                     \
+    const uint32_t qb_ = S * (vq);                                                         \
+    const uint32_t sh_ = qb_ & 3u;                                                         \
+    const uint8_t* w_ = stage + (qb_ & ~3u);                                               \
+    const uint32_t xc_ = *reinterpret_cast<const uint32_t*>(w_);                           \
+    const uint32_t sel_ = __builtin_amdgcn_perm(sh_, sh_, 0u) + (S == 1 ? 0u : 0x01000100u); \
+    const uint32_t xr_ = __builtin_amdgcn_perm(xc_, xc_, sel_);                            \
+    _Pragma("unroll") for (int j_ = 0; j_ < NC; ++j_) {                                    \
+      const uint32_t* p_ = reinterpret_cast<const uint32_t*>(w_ + woff[j_]);               \
+      z[j_] = differs<S>(__builtin_amdgcn_alignbyte(p_[1], p_[0], sh_), xr_);              \
+    }                                                                                      \
+  } while (0)
+#define GPULZ_DENSE_REC(val)    \
+  do {                          \
+    if (lane == nb) lo = (val); \
+    if (++nb == 64) {           \
+      flush(lo);                \
+      nb = 0;                   \
+    }                           \
+  } while (0)
+
+  // LDS byte address of the stage (the window dwords the inner loop reads):
+  // the low 32 bits of the generic address (the shared aperture starts on a
+  // 4 GiB boundary)
+  const uint32_t stage_lds = (uint32_t)(uintptr_t)stage;
+  uint32_t z[NC];
+  bool have_z = false;  // z holds position h's compare already
+  uint32_t h = 0;
+  uint32_t vq;  // next position to compare, in a vector register
+  asm volatile("v_mov_b32 %0, 0" : "=v"(vq));
+  while (h < c) {
+    if (!have_z) {
+      GPULZ_DENSE_COMPARE(vq);
+      vq += 1;
+    }
+    uint32_t live[NC];
+    if (h < W) {
+#pragma unroll
+      for (int j = 0; j < NC; ++j) live[j] = wm[j] & SM::mask_le(j, h, lane) & ~z[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NC; ++j) live[j] = wm[j] & ~z[j];
+    }
+    if (!SM::any(live)) {
+      GPULZ_DENSE_REC(h << 1);  // a literal
+      have_z = false;
+      ++h;
+      continue;
+    }
+    // extend through h + 1 .. h + steps while some offset still matches
+    const uint32_t steps = min(kMaxMatch, c - h) - 1;
+    uint32_t n = 0;
+    if constexpr (NC == 1) {
+      const uint32_t qb = S * (h + 1);
+      extend_run<S>(live[0], n, z[0], steps, stage_lds + (qb & ~3u), qb & 3u, (uint32_t)woff[0]);
+      have_z = n < steps;  // then z holds the compare of h + 1 + n: the next token's start
+      vq = h + 2 + n - (have_z ? 0u : 1u);
+    } else {
+      have_z = false;
+      for (;;) {
+        if (n == steps) break;
+        GPULZ_DENSE_COMPARE(vq);
+        vq += 1;
+        uint32_t nl[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) nl[j] = live[j] & ~z[j];
+        if (!SM::any(nl)) {
+          have_z = true;  // the compare of h + 1 + n: the next token's start
+          break;
+        }
+#pragma unroll
+        for (int j = 0; j < NC; ++j) live[j] = nl[j];
+        ++n;
+      }
+    }
+    uint32_t t = n + 1;
+    if (t < MIN) {
+      GPULZ_DENSE_REC(h << 1);
+    } else {
+      // the largest live offset: the highest lane with a live bit, its
+      // lowest live part (each lane works out its own, one lane is read)
+      uint32_t dl = 0;
+      int col = -1;
+#pragma unroll
+      for (int j = NC - 1; j >= 0; --j) {
+        if (col < 0 && ballot(live[j] != 0) != 0) col = j;
+      }
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        if (j == col) {
+          dl = (uint32_t)(j * SM::P::kPerCol + SM::P::K * lane + SM::P::K) -
+               (uint32_t)__builtin_ctz(live[j] | 0x80000000u) / (8 * S);
+        }
+      }
+      const uint64_t b = ballot(live[col] != 0);
+      const uint32_t d = readlane(dl, 63u - (uint32_t)__builtin_clzll(b));
+      if (d >= t) {
+        GPULZ_DENSE_REC(1u | (t << 1) | ((d & 0xFFu) << 9));
+      } else {
+        // periodic run: the capped search decides, then resume at its end
+        const uint32_t key = search_token<S, WC>(win, h, c, W, MIN, wmask64, lane);
+        GPULZ_DENSE_REC(key ? 1u | ((key >> 9) << 1) | ((key & 0xFFu) << 9) : h << 1);
+        t = key ? key >> 9 : 1u;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(vq) : "s"(h + t));
+        have_z = false;
+      }
+    }
+    h += t;
+  }
+#undef GPULZ_DENSE_COMPARE
+#undef GPULZ_DENSE_REC
+  dlo = lo;
+  return nb;
+}
+
 // ---- single-pass output: record offsets by decoupled look-back -------------
 //
 // A chunk's record offset is the sum of the record sizes before it (the
@@ -657,11 +1136,31 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
   // pointer only if p or p + 1 is an even hit; the parse widens the bitmap
   // accordingly (candidates are a superset of pointer starts, and every
   // candidate still gets the exact search).
+  //
+  // Dense chunks (streaming search, one wave per chunk): the streaming
+  // search compares every position it passes anyway, so the bitmap only
+  // pays where it lets the parse skip literal runs. If at least 3/4 of the
+  // tested positions of the first block are hits, the rest of the bitmap is
+  // not built and every position is a candidate.
   const bool sampled = job.MIN >= 2;
+  bool dense = false;
   {
     const uint4* w4 = reinterpret_cast<const uint4*>(stage);
     const uint32_t nblocks = (c + kBlock - 1) / kBlock;
-    for (uint32_t b = wave; b < nblocks; b += nwaves) {
+    uint32_t b0 = wave;
+    if constexpr (kStreamSearch<S>) {
+      if (nwaves == 1 && nblocks > 1) {
+        if (sampled) hit_block<S, true, 2>(w4, 0, job.W, hits);
+        else hit_block<S, true, 1>(w4, 0, job.W, hits);
+        wave_sync();
+        constexpr uint32_t kWords = kBlock / 32;
+        const uint32_t cnt = lane < kWords ? (uint32_t)__popc(hits[lane]) : 0u;
+        const uint32_t tested = sampled ? kBlock / 2 : kBlock;
+        dense = 4 * readlane(wave_incl_scan(cnt), 63) >= 3 * tested;
+        b0 = dense ? nblocks : 1;
+      }
+    }
+    for (uint32_t b = b0; b < nblocks; b += nwaves) {
       const uint32_t base = b * kBlock;
       if (sampled) {
         if (base >= job.W) hit_block<S, false, 2>(w4, base, job.W, hits);
@@ -684,8 +1183,21 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
   uint8_t* slot = job.slot;
   uint32_t ntok = 0, pay = 0, desc = 0, g0 = kNoGroup;
   uint32_t p = 0;
+  if constexpr (kStreamSearch<S>) {
+    if (dense && job.MIN <= 2) {
+      const uint32_t rest = parse_dense<S, WC>(stage, c, job.W, job.MIN, wmask, lane, desc,
+                                               [&](uint32_t d64) {
+        emit_group<S, kSinglePass>(64, d64, ntok >> 6, win, slot, job.flag_area, pay, g0);
+        ntok += 64;
+      });
+      ntok += rest;
+      p = c;
+    }
+  }
   CandCursor cc;
   cc.init(hits, nhw, sampled);
+  StreamMatchFor<S, WC> sm;
+  sm.init(stage, job.W, lane);
   while (p < c) {
     const uint32_t h = cc.next(p, c, hits, nhw, sampled);
     // literals for [p, h); on the single-pass path, whole all-literal groups
@@ -709,7 +1221,7 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
     }
     if (h >= c) break;
 
-    const uint32_t key = search_token<S, WC>(win, h, c, job.W, job.MIN, wmask, lane);
+    const uint32_t key = find_token<S, WC>(sm, win, h, c, job.W, job.MIN, wmask, lane);
     uint32_t val;
     if (key) {
       val = 1u | ((key >> 9) << 1) | ((key & 0xFFu) << 9);
@@ -828,6 +1340,8 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
 #pragma unroll
   for (int col = 0; col < WC; ++col) wmask[col] = ballot(64u * col + lane + 1u <= job.W);
   const uint32_t seg = (c + nwaves - 1) / nwaves;
+  StreamMatchFor<S, WC> sm;
+  sm.init(stage, job.W, lane);
 
   // ---- each wave: the greedy parse of its own segment
   {
@@ -843,7 +1357,7 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
         p = e;
         continue;
       }
-      const uint32_t key = search_token<S, WC>(win, p, c, job.W, job.MIN, wmask, lane);
+      const uint32_t key = find_token<S, WC>(sm, win, p, c, job.W, job.MIN, wmask, lane);
       if (lane == 0) {
         atomicOr(&tok[p >> 5], 1u << (p & 31u));
         if (key) {
@@ -868,7 +1382,7 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
     while (q < n1 && !((tok[q >> 5] >> (q & 31u)) & 1u)) {
       const uint32_t h = cc.next(q, c, hits, nhw, sampled);
       uint32_t key = 0;
-      if (h == q) key = search_token<S, WC>(win, q, c, job.W, job.MIN, wmask, lane);
+      if (h == q) key = find_token<S, WC>(sm, win, q, c, job.W, job.MIN, wmask, lane);
       if (lane == 0) {
         atomicOr(&xtok[q >> 5], 1u << (q & 31u));
         if (key) {
@@ -918,7 +1432,7 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
       while (q < s1 && !((tok[q >> 5] >> (q & 31u)) & 1u)) {
         const uint32_t h = cc.next(q, c, hits, nhw, sampled);
         uint32_t key = 0;
-        if (h == q) key = search_token<S, WC>(win, q, c, job.W, job.MIN, wmask, lane);
+        if (h == q) key = find_token<S, WC>(sm, win, q, c, job.W, job.MIN, wmask, lane);
         const uint32_t L = key ? key >> 9 : 1u;
         if (lane == 0) {
           atomicOr(&tok[q >> 5], 1u << (q & 31u));
@@ -1065,7 +1579,7 @@ __device__ void encode_chunk_scan(const ChunkJob& job, uint8_t* lds) {
       uint32_t w = p > job.W ? p - job.W : 0, b = p, len = 0, off = 0;
       while (w < p && b < c) {
         const bool eq = (len < kMaxMatch) & (win[b] == win[w]);
-        off = eq & (len == 0) ? p - w : off;
+        off = (eq & (len == 0)) ? p - w : off;
         const bool better = !eq & (len > bestL);
         bestL = better ? len : bestL;
         bestd = better ? off : bestd;

@@ -1,6 +1,8 @@
 // C ABI: argument checks, workspace layout, kernel launches.
 #include "gpulz.h"
 
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -38,6 +40,19 @@ void prof_end(int idx, hipStream_t s) {
   if (idx < 0) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEventRecord(g_prof_events[idx].stop, s);
+}
+
+// Launch checks read hipGetLastError, which also holds the error of any
+// earlier failed HIP call on this thread (the caller's, or a framework's);
+// entry points clear it right before their first launch so that their
+// return value reports their own launches only.
+void clear_stale_hip_error() { (void)hipGetLastError(); }
+
+// A failed launch or runtime call: GPULZ_ERR_HIP (with the HIP error named on
+// stderr if GPULZ_DEBUG is set in the environment).
+gpulz_status hip_failed(hipError_t e, const char* what) {
+  if (getenv("GPULZ_DEBUG")) fprintf(stderr, "gpulz: %s: %s\n", what, hipGetErrorName(e));
+  return GPULZ_ERR_HIP;
 }
 
 bool valid_params(uint32_t S, uint32_t C, uint32_t W, uint32_t MIN) {
@@ -215,13 +230,16 @@ gpulz_status gpulz_compress_policy(const void* d_in, uint64_t nbytes, uint32_t S
     waves = g_defaults[width_index(S)].waves_per_chunk;
   }
   int pi = prof_begin(1, stream);
-  if (launch_fused_prep(a, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  clear_stale_hip_error();
+  hipError_t err = launch_fused_prep(a, stream);
+  if (err != hipSuccess) return hip_failed(err, "compress prepare launch");
   prof_end(pi, stream);
   pi = prof_begin(0, stream);
   for (uint64_t c0 = 0; c0 < N; c0 += kMaxChunksPerLaunch) {
     a.chunk0 = c0;
     a.nchunks = N - c0 < kMaxChunksPerLaunch ? N - c0 : kMaxChunksPerLaunch;
-    if (launch_fused_encode(a, waves, stream) != hipSuccess) return GPULZ_ERR_HIP;
+    if ((err = launch_fused_encode(a, waves, stream)) != hipSuccess)
+      return hip_failed(err, "compress encode launch");
     ++a.launch;
   }
   prof_end(pi, stream);
@@ -285,10 +303,13 @@ gpulz_status gpulz_decompress(const void* d_in, uint64_t in_bytes, void* d_out, 
   da.out = static_cast<uint8_t*>(d_out);
   da.status = d_status;
   int pi = prof_begin(3, stream);
-  if (launch_decode_prepare(pa, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  clear_stale_hip_error();
+  hipError_t err = launch_decode_prepare(pa, stream);
+  if (err != hipSuccess) return hip_failed(err, "decompress prepare launch");
   prof_end(pi, stream);
   pi = prof_begin(4, stream);
-  if (launch_decode_chunks(da, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  if ((err = launch_decode_chunks(da, stream)) != hipSuccess)
+    return hip_failed(err, "decompress launch");
   prof_end(pi, stream);
   return GPULZ_OK;
 }
@@ -357,7 +378,9 @@ gpulz_status gpulz_compress_batch(uint64_t nbufs, const void* const* d_in_ptrs,
   a.max_chunks = l.max_chunks;
   a.slot_cap = l.slot_cap;
   int pi = prof_begin(5, stream);
-  if (launch_compress_batch(a, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  clear_stale_hip_error();
+  const hipError_t err = launch_compress_batch(a, stream);
+  if (err != hipSuccess) return hip_failed(err, "compress batch launch");
   prof_end(pi, stream);
   return GPULZ_OK;
 }
@@ -396,7 +419,9 @@ gpulz_status gpulz_decompress_batch(uint64_t nbufs, const void* const* d_in_ptrs
   a.group_off = reinterpret_cast<uint64_t*>(ws + l.groups_off);
   a.group_cap = l.group_cap;
   int pi = prof_begin(6, stream);
-  if (launch_decompress_batch(a, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  clear_stale_hip_error();
+  const hipError_t err = launch_decompress_batch(a, stream);
+  if (err != hipSuccess) return hip_failed(err, "decompress batch launch");
   prof_end(pi, stream);
   return GPULZ_OK;
 }
@@ -449,7 +474,9 @@ gpulz_status gpulz_huff_compress(const void* d_in, uint64_t nbytes, const uint64
   a.out_bytes = d_out_bytes;
   a.status = d_status;
   const int pi = prof_begin(7, stream);
-  if (huff::launch_compress(a, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  clear_stale_hip_error();
+  const hipError_t err = huff::launch_compress(a, stream);
+  if (err != hipSuccess) return hip_failed(err, "huffman compress launch");
   prof_end(pi, stream);
   return GPULZ_OK;
 }
@@ -480,7 +507,9 @@ gpulz_status gpulz_huff_decompress(const void* d_in, uint64_t in_bytes, void* d_
   a.out_bytes = d_out_bytes;
   a.status = d_status;
   const int pi = prof_begin(8, stream);
-  if (huff::launch_decompress(a, stream) != hipSuccess) return GPULZ_ERR_HIP;
+  clear_stale_hip_error();
+  const hipError_t err = huff::launch_decompress(a, stream);
+  if (err != hipSuccess) return hip_failed(err, "huffman decompress launch");
   prof_end(pi, stream);
   return GPULZ_OK;
 }

@@ -12,7 +12,9 @@ A request's latency is its completion (a device event after its batch)
 minus its scheduled arrival.
 
 `Scheduler` is the pure admission logic; `DeviceBackend` runs batches on
-the GPU through the batch C ABI; `serve` drives either with a clock.
+the GPU through the batch C ABI, `PlainBackend` runs the same admitted
+requests one gpulz_compress / gpulz_decompress call each (the plain path it
+is measured against); `serve` drives any of them with a clock.
 """
 from __future__ import annotations
 
@@ -98,8 +100,9 @@ def serve(trace, backend, budget_bytes: int, slots: int = 3, max_batch: int = 51
             if t is None:
                 still.append((handle, batch))
             else:
-                for r in batch:
-                    r.done = t
+                # one completion time for the batch, or one per request
+                for k, r in enumerate(batch):
+                    r.done = t[k] if isinstance(t, list) else t
                 backend.release(handle, batch)
                 sched.finish(batch)
         running = still
@@ -223,6 +226,55 @@ class DeviceBackend:
                         r.result = o[:n]
 
 
+class PlainBackend(DeviceBackend):
+    """The plain path under the same admission: each admitted request is one
+    gpulz_compress or gpulz_decompress call of its own (with its own
+    workspace), issued in arrival order on the batch's stream, and completes
+    at its own device event."""
+
+    def launch(self, batch):
+        torch, gpulz = self.torch, self.gpulz
+        stream = self.streams[self.k % len(self.streams)]
+        self.k += 1
+        keep = []
+        with torch.cuda.stream(stream):
+            for r in batch:
+                out = torch.empty(max(r.out_cap, 1), dtype=torch.uint8, device="cuda")
+                meta = torch.zeros(2, dtype=torch.int64, device="cuda")
+                if r.op == COMPRESS:
+                    C, W, MIN, _ = gpulz.gpulz_default_params(r.symbol_bytes)
+                    ws_bytes = gpulz.gpulz_compress_workspace_size(r.nbytes, r.symbol_bytes, C)
+                    ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device="cuda")
+                    st = gpulz.gpulz_compress(r.src.data_ptr(), r.nbytes, r.symbol_bytes, C, W, MIN,
+                                              out.data_ptr(), r.out_cap, meta.data_ptr(),
+                                              meta.data_ptr() + 8, ws.data_ptr(), ws_bytes,
+                                              stream.cuda_stream)
+                else:
+                    ws_bytes = gpulz.gpulz_decompress_workspace_size(r.nbytes)
+                    ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device="cuda")
+                    st = gpulz.gpulz_decompress(r.src.data_ptr(), r.nbytes, out.data_ptr(),
+                                                r.out_cap, meta.data_ptr(), meta.data_ptr() + 8,
+                                                ws.data_ptr(), ws_bytes, stream.cuda_stream)
+                if st != gpulz.GPULZ_OK:
+                    raise gpulz.GpulzError(st, f"plain {r.op}")
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(stream)
+                keep.append((out, meta, ws, ev))
+        return keep
+
+    def poll(self, handle):
+        if not handle[-1][3].query():
+            return None
+        return [self.start_event.elapsed_time(ev) / 1e3 for _, _, _, ev in handle]
+
+    def release(self, handle, batch):
+        for r, (out, meta, _, _) in zip(batch, handle):
+            n, status = meta.cpu().tolist()
+            r.status = status & 0xFFFFFFFF
+            if self.keep:
+                r.result = out[:n]
+
+
 # ---- workload -------------------------------------------------------------------
 
 def make_trace(rate: float, duration: float, seed: int, compress_frac: float = 0.7,
@@ -316,19 +368,25 @@ def main_bench(args):
     del bd
     torch.cuda.empty_cache()
     runs = [(args.serve_rate, args.serve_seconds)] + [(r, args.sweep_seconds) for r in args.sweep_rates]
+    backends = {"batched": DeviceBackend, "plain": PlainBackend}
     for rate, dur in runs:
-        trace = make_trace(rate, dur, seed=4)
-        reqs = build_requests(trace, pools, streams)
-        log(f"rate {rate}/s for {dur} s: {len(reqs)} requests")
-        backend = DeviceBackend(nstreams=args.serve_slots)
-        t0 = time.perf_counter()
-        sched = serve(reqs, backend, args.budget_gb * 10**9, slots=args.serve_slots,
-                      progress=lambda now, p, q, r, b: log(
-                          f"t={now:.1f}s pending={p} queued={q} running={r} inflight={b / 1e9:.1f} GB"))
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        res = summarize(reqs, wall, rate, dur)
-        res.update({"metric": "serving throughput and p50/p99 latency", "workload": f"serve-{rate}",
-                    "budget_GB": args.budget_gb, "slots": args.serve_slots,
-                    "rejected": len(sched.rejected), "duration_s": dur})
-        print(json.dumps(res), flush=True)
+        for name in getattr(args, "serve_backends", ["batched", "plain"]):
+            trace = make_trace(rate, dur, seed=4)
+            reqs = build_requests(trace, pools, streams)
+            log(f"{name}: rate {rate}/s for {dur} s: {len(reqs)} requests")
+            backend = backends[name](nstreams=args.serve_slots)
+            t0 = time.perf_counter()
+            sched = serve(reqs, backend, args.budget_gb * 10**9, slots=args.serve_slots,
+                          progress=lambda now, p, q, r, b: log(
+                              f"t={now:.1f}s pending={p} queued={q} running={r} "
+                              f"inflight={b / 1e9:.1f} GB"))
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            res = summarize(reqs, wall, rate, dur)
+            res.update({"metric": "serving throughput and p50/p99 latency",
+                        "workload": f"serve-{name}-{rate}", "backend": name,
+                        "budget_GB": args.budget_gb, "slots": args.serve_slots,
+                        "rejected": len(sched.rejected), "duration_s": dur})
+            print(json.dumps(res), flush=True)
+            del reqs, backend, sched
+            torch.cuda.empty_cache()
