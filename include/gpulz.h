@@ -163,6 +163,22 @@ gpulz_status gpulz_decompress(const void* d_in, uint64_t in_bytes, void* d_out,
                               uint64_t out_capacity, uint64_t* d_out_bytes, int32_t* d_status,
                               void* d_workspace, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * decompression as gpulz_decompress, with the workspace taken from a
+ * library-owned device array instead of a caller's buffer. The array holds
+ * 13,422,080 bytes on each GPU the library runs on, kept until the process
+ * ends; it serves streams of at most 2^30 bytes (GPULZ_ERR_WORKSPACE,
+ * nothing launched, for a larger in_bytes). Calls on one GPU share that
+ * array: calls that overlap on one GPU (different streams, or host threads)
+ * race and must be serialised by the caller. The array needs no clearing
+ * between calls (each call rewrites what it reads). Arguments, outcomes and
+ * asynchrony as gpulz_decompress; the first call on a device also looks up
+ * the array's address there (GPULZ_ERR_HIP if that fails). */
+gpulz_status gpulz_decompress_noalloc(const void* d_in, uint64_t in_bytes, void* d_out,
+                                      uint64_t out_capacity, uint64_t* d_out_bytes,
+                                      int32_t* d_status, hipStream_t stream);
+
 /* ---- batches ------------------------------------------------------------
  * Many buffers, each with its own size and symbol width, compressed or
  * decompressed by one fixed sequence of launches on one stream (a plan

@@ -314,6 +314,57 @@ gpulz_status gpulz_decompress(const void* d_in, uint64_t in_bytes, void* d_out, 
   return GPULZ_OK;
 }
 
+// ---- decompression without allocation ---------------------------------------
+//
+// gpulz_decompress_noalloc takes its workspace from a file-scope device
+// array instead of a caller's buffer. Each GPU the library runs on holds its
+// own copy until the process ends. Host code never passes the array's name
+// to a kernel (in host code it is a stand-in, not a device address): its
+// device address is looked up once per device, with that device current,
+// and kept. The decoder writes every byte of its workspace it later reads
+// (the stream parameters, then every record-offset group), so nothing has to
+// be cleared between calls.
+constexpr uint64_t kNoAllocMaxStreamBytes = 1ull << 30;
+constexpr size_t kNoAllocScratchBytes =
+    (size_t)align_up(256 + 8 * decode_group_slots(kNoAllocMaxStreamBytes), 256);
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's scratch address (looked up on the device's first call).
+gpulz_status current_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GPULZ_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GPULZ_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GPULZ_OK;
+}
+
+}  // namespace
+
+gpulz_status gpulz_decompress_noalloc(const void* d_in, uint64_t in_bytes, void* d_out,
+                                      uint64_t out_capacity, uint64_t* d_out_bytes,
+                                      int32_t* d_status, hipStream_t stream) {
+  if (in_bytes > kNoAllocMaxStreamBytes) return GPULZ_ERR_WORKSPACE;
+  size_t need = 0;
+  gpulz_decompress_workspace_size(in_bytes, &need);
+  if (need > kNoAllocScratchBytes) return GPULZ_ERR_WORKSPACE;
+  void* ws = nullptr;
+  const gpulz_status st = current_scratch(&ws);
+  if (st != GPULZ_OK) return st;
+  return gpulz_decompress(d_in, in_bytes, d_out, out_capacity, d_out_bytes, d_status, ws, need,
+                          stream);
+}
+
 gpulz_status gpulz_default_params(uint32_t S, gpulz_params* params) {
   const int w = width_index(S);
   if (w < 0 || !params) return GPULZ_ERR_INVALID_ARG;

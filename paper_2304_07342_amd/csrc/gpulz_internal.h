@@ -110,13 +110,13 @@ struct DecodeParams {
 
 // Upper bound on the chunks of a valid stream: every chunk costs at least 8
 // table bytes, 1 flag byte and 1 payload byte.
-__host__ __device__ inline uint64_t decode_max_chunks(uint64_t stream_bytes) {
+__host__ __device__ constexpr uint64_t decode_max_chunks(uint64_t stream_bytes) {
   return stream_bytes > kHeaderBytes ? (stream_bytes - kHeaderBytes) / 10 : 0;
 }
 
 // Record offsets are kept for every 64th chunk (a chunk's own offset is its
 // group's plus a wave prefix sum over the group's table entries).
-__host__ __device__ inline uint64_t decode_group_slots(uint64_t stream_bytes) {
+__host__ __device__ constexpr uint64_t decode_group_slots(uint64_t stream_bytes) {
   return (decode_max_chunks(stream_bytes) + 63) / 64 + 1;
 }
 

@@ -26,7 +26,8 @@ GPULZ_ERR_UNSUPPORTED = 6
 EXPORTS = (
     "gpulz_abi_version", "gpulz_status_string", "gpulz_compress_bound",
     "gpulz_compress_workspace_size", "gpulz_compress", "gpulz_compress_policy", "gpulz_peek_header",
-    "gpulz_decompress_workspace_size", "gpulz_decompress", "gpulz_default_params",
+    "gpulz_decompress_workspace_size", "gpulz_decompress", "gpulz_decompress_noalloc",
+    "gpulz_default_params",
     "gpulz_set_default_params", "gpulz_compress_batch_workspace_size", "gpulz_compress_batch",
     "gpulz_decompress_batch_workspace_size", "gpulz_decompress_batch", "gpulz_profile_enable",
     "gpulz_profile_read", "gpulz_huff_compress_bound", "gpulz_huff_compress_workspace_size",
@@ -93,6 +94,8 @@ def lib() -> ctypes.CDLL:
         L.gpulz_decompress_workspace_size.argtypes = [u64, ctypes.POINTER(sz)]
         L.gpulz_decompress.restype = ctypes.c_int
         L.gpulz_decompress.argtypes = [vp, u64, vp, u64, vp, vp, vp, sz, vp]
+        L.gpulz_decompress_noalloc.restype = ctypes.c_int
+        L.gpulz_decompress_noalloc.argtypes = [vp, u64, vp, u64, vp, vp, vp]
         L.gpulz_default_params.restype = ctypes.c_int
         L.gpulz_default_params.argtypes = [u32, ctypes.POINTER(Params)]
         L.gpulz_set_default_params.restype = ctypes.c_int
@@ -188,6 +191,12 @@ def gpulz_decompress(d_in: int, in_bytes: int, d_out: int, out_capacity: int, d_
                      d_status: int, d_workspace: int, ws_bytes: int, stream: int = 0) -> int:
     return lib().gpulz_decompress(d_in, in_bytes, d_out, out_capacity, d_out_bytes, d_status,
                                   d_workspace, ws_bytes, stream)
+
+
+def gpulz_decompress_noalloc(d_in: int, in_bytes: int, d_out: int, out_capacity: int,
+                             d_out_bytes: int, d_status: int, stream: int = 0) -> int:
+    return lib().gpulz_decompress_noalloc(d_in, in_bytes, d_out, out_capacity, d_out_bytes,
+                                          d_status, stream)
 
 
 def gpulz_huff_compress_bound(nbytes: int) -> int:

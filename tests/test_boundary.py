@@ -55,6 +55,13 @@ def test_workspace_sizes_grow_with_input():
     assert gpulz.gpulz_decompress_workspace_size(1 << 20) < gpulz.gpulz_decompress_workspace_size(1 << 24)
 
 
+def test_noalloc_decompress_rejects_streams_over_its_limit():
+    # checked on the host before any HIP call (no GPU needed)
+    FAKE = 1 << 20
+    assert gpulz.gpulz_decompress_noalloc(FAKE, (1 << 30) + 1, FAKE, 1, FAKE, FAKE + 8, 0) == \
+        gpulz.GPULZ_ERR_WORKSPACE
+
+
 def test_peek_header_on_oracle_streams():
     for S, n in [(1, 0), (2, 11), (4, 4096), (8, 29)]:
         s = oracle.compress(bytes(range(256)) * (n // 256) + bytes(n % 256), S, 64, 16, 2)
