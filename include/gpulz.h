@@ -72,7 +72,7 @@ typedef enum {
 uint32_t gpulz_abi_version(void);
 
 /* Static string naming a status code ("unknown status" for other values). */
-const char* gpulz_status_string(int32_t status);
+const char* gpulz_status_string(gpulz_status status);
 
 /* Largest stream gpulz_compress can produce for these parameters: header,
  * table, and for every chunk of c symbols ceil(c/8) flag bytes plus c*k
@@ -146,9 +146,12 @@ gpulz_status gpulz_compress_policy(const void* d_in, uint64_t nbytes, uint32_t s
 gpulz_status gpulz_peek_header(const void* h_header, size_t header_bytes, uint64_t* nbytes,
                                uint32_t* symbol_bytes, uint64_t* stream_bytes);
 
-/* Workspace bytes gpulz_decompress needs for a stream of `stream_bytes`.
- * Host-only. */
-gpulz_status gpulz_decompress_workspace_size(uint64_t stream_bytes, size_t* ws_bytes);
+/* Workspace bytes gpulz_decompress needs for a stream of `comp_bytes` whose
+ * decompressed size is `nbytes` (0 if not known). The size is that of the
+ * most chunks a stream of comp_bytes can hold (the decoder rejects a header
+ * that claims more), so it does not depend on nbytes. Host-only. */
+gpulz_status gpulz_decompress_workspace_size(uint64_t comp_bytes, uint64_t nbytes,
+                                             size_t* ws_bytes);
 
 /* Decompress the stream d_in[0..in_bytes) into d_out. The decoder checks
  * every rule of the layout (header fields, table sums, flag and payload

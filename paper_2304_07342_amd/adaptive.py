@@ -51,31 +51,41 @@ def decide(element_bytes: int, level: int, multi_byte_ratio: float | None, min_m
                 min_match, multi_byte_ratio)
 
 
+def _plan_with_streams(fields, element_bytes: int, level: int, min_match: int,
+                       threshold: float):
+    """The plan, and the multi-byte streams measured for it (None for
+    single-byte elements)."""
+    if element_bytes not in (1, 2, 4, 8):
+        raise ValueError("element_bytes must be 1, 2, 4 or 8")
+    if element_bytes == 1:
+        return decide(1, level, None, min_match), None
+    S = element_bytes
+    C = gpulz.gpulz_default_params(S)[0]
+    W = multi_byte_window(S, level)
+    ratios, streams = [], []
+    for f in fields:
+        n = f.numel()
+        s = gpulz.compress(f, S, C, W, min_match)
+        streams.append(s)
+        if n:
+            ratios.append(n / s.numel())
+    avg = sum(ratios) / len(ratios) if ratios else None
+    return decide(S, level, avg, min_match, threshold=threshold), streams
+
+
 def plan(fields, element_bytes: int, level: int = 3, min_match: int = 2,
          threshold: float = RATIO_THRESHOLD) -> Plan:
     """Measure the average multi-byte ratio over `fields` (uint8 device
     tensors of one dataset) and apply the rule."""
-    if element_bytes not in (1, 2, 4, 8):
-        raise ValueError("element_bytes must be 1, 2, 4 or 8")
-    if element_bytes == 1:
-        return decide(1, level, None, min_match)
-    S = element_bytes
-    C = gpulz.gpulz_default_params(S)[0]
-    W = multi_byte_window(S, level)
-    ratios = []
-    for f in fields:
-        n = f.numel()
-        if n == 0:
-            continue
-        s = gpulz.compress(f, S, C, W, min_match)
-        ratios.append(n / s.numel())
-    avg = sum(ratios) / len(ratios) if ratios else None
-    return decide(S, level, avg, min_match, threshold=threshold)
+    return _plan_with_streams(fields, element_bytes, level, min_match, threshold)[0]
 
 
 def compress(fields, element_bytes: int, level: int = 3, min_match: int = 2):
     """Compress every field with the plan chosen for the dataset; returns
-    (plan, [streams])."""
-    p = plan(fields, element_bytes, level, min_match)
+    (plan, [streams]). When the plan keeps the multi-byte width, the streams
+    measured for the decision are the result (same parameters)."""
+    p, measured = _plan_with_streams(fields, element_bytes, level, min_match, RATIO_THRESHOLD)
+    if measured is not None and p.symbol_bytes == element_bytes:
+        return p, measured
     return p, [gpulz.compress(f, p.symbol_bytes, p.chunk_symbols, p.window, p.min_match)
                for f in fields]

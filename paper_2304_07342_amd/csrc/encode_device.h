@@ -5,6 +5,7 @@
 #include <type_traits>
 
 #include "gpulz_internal.h"
+#include "dense_asm.h"
 #include "stream_device.h"
 #include "wave.h"
 
@@ -837,7 +838,49 @@ __device__ __forceinline__ uint32_t parse_dense(const uint8_t* stage, uint32_t c
   uint32_t h = 0;
   uint32_t vq;  // next position to compare, in a vector register
   asm volatile("v_mov_b32 %0, 0" : "=v"(vq));
+  // From each group-aligned token start the group loop (dense_groups) takes
+  // over, until a flush, a capped token (redone here first, then the group
+  // loop again) or the chunk's last groups (finished here).
+  constexpr uint32_t kPh = 4 / S;  // positions per dword group
+  bool fast_ok = true, skip_fast = false;
+  uint32_t hi = 0;
+  const uint32_t dk = (4 / S) * lane + 4 / S;  // largest offset of this lane in column 0
   while (h < c) {
+    if (fast_ok && !skip_fast && (h & (kPh - 1)) == 0 && h + kPh < c) {
+      uint32_t q = h, hh = h, t = 0, tlim = 0, code;
+      uint32_t lv[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) lv[j] = 0;
+      for (;;) {
+        nb = __builtin_amdgcn_readfirstlane(nb);  // uniform (the compiler cannot tell)
+        code = dense_groups<S, NC>(q, hh, t, tlim, nb, lv, lo, hi, c, W, MIN, stage_lds,
+                                   (uint32_t)woff[0], lane, dk, wm, SM::P::kLive);
+        if (code != kDenseFlush) break;
+        flush(lo);
+        lo = hi;
+        nb -= 64;
+        if (q + kPh >= c) {
+          code = kDenseTail;
+          break;
+        }
+      }
+      if (nb >= 64) {
+        flush(lo);
+        lo = hi;
+        nb -= 64;
+      }
+      if (code == kDenseCapped) {
+        h = hh;
+        skip_fast = true;
+      } else {
+        h = t ? hh : q;
+        fast_ok = false;
+      }
+      have_z = false;
+      asm volatile("v_mov_b32 %0, %1" : "=v"(vq) : "s"(h));
+      continue;
+    }
+    skip_fast = false;
     if (!have_z) {
       GPULZ_DENSE_COMPARE(vq);
       vq += 1;

@@ -151,9 +151,9 @@ BatchDecLayout batch_dec_layout(uint64_t nbufs, uint64_t max_total) {
 
 extern "C" {
 
-uint32_t gpulz_abi_version(void) { return 100; }
+uint32_t gpulz_abi_version(void) { return 101; }
 
-const char* gpulz_status_string(int32_t status) {
+const char* gpulz_status_string(gpulz_status status) {
   switch (status) {
     case GPULZ_OK: return "ok";
     case GPULZ_ERR_INVALID_ARG: return "invalid argument";
@@ -271,9 +271,14 @@ gpulz_status gpulz_peek_header(const void* h_header, size_t header_bytes, uint64
   return GPULZ_OK;
 }
 
-gpulz_status gpulz_decompress_workspace_size(uint64_t stream_bytes, size_t* ws_bytes) {
+gpulz_status gpulz_decompress_workspace_size(uint64_t comp_bytes, uint64_t nbytes,
+                                             size_t* ws_bytes) {
   if (!ws_bytes) return GPULZ_ERR_INVALID_ARG;
-  *ws_bytes = (size_t)(256 + 8 * decode_group_slots(stream_bytes));
+  // one record-offset slot per 64 chunks of the most a stream of comp_bytes
+  // can hold (the decoder accepts no header claiming more); the size does
+  // not depend on nbytes
+  (void)nbytes;
+  *ws_bytes = (size_t)(256 + 8 * decode_group_slots(comp_bytes));
   return GPULZ_OK;
 }
 
@@ -284,7 +289,7 @@ gpulz_status gpulz_decompress(const void* d_in, uint64_t in_bytes, void* d_out, 
     return GPULZ_ERR_INVALID_ARG;
   if (!aligned(d_in, 16) || !aligned(d_out, 16) || !aligned(d_ws, 256)) return GPULZ_ERR_INVALID_ARG;
   size_t need = 0;
-  gpulz_decompress_workspace_size(in_bytes, &need);
+  gpulz_decompress_workspace_size(in_bytes, 0, &need);
   if (!d_ws || ws_bytes < need) return GPULZ_ERR_WORKSPACE;
   uint8_t* ws = static_cast<uint8_t*>(d_ws);
   DecodePrepArgs pa;
@@ -356,7 +361,7 @@ gpulz_status gpulz_decompress_noalloc(const void* d_in, uint64_t in_bytes, void*
                                       int32_t* d_status, hipStream_t stream) {
   if (in_bytes > kNoAllocMaxStreamBytes) return GPULZ_ERR_WORKSPACE;
   size_t need = 0;
-  gpulz_decompress_workspace_size(in_bytes, &need);
+  gpulz_decompress_workspace_size(in_bytes, 0, &need);
   if (need > kNoAllocScratchBytes) return GPULZ_ERR_WORKSPACE;
   void* ws = nullptr;
   const gpulz_status st = current_scratch(&ws);

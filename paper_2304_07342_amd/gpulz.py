@@ -71,6 +71,12 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run paper_2304_07342_amd/build.py")
+        # torch carries its own HIP runtime, which it loads by file name; the
+        # library asks for the runtime by soname. Loading torch first makes
+        # the library bind to that same runtime: loaded the other way round,
+        # the process would hold two HIP runtimes and the library's would
+        # find no device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         u32, u64, i32, sz, vp = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t,
                                  ctypes.c_void_p)
@@ -91,7 +97,7 @@ def lib() -> ctypes.CDLL:
         L.gpulz_peek_header.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(u64),
                                         ctypes.POINTER(u32), ctypes.POINTER(u64)]
         L.gpulz_decompress_workspace_size.restype = ctypes.c_int
-        L.gpulz_decompress_workspace_size.argtypes = [u64, ctypes.POINTER(sz)]
+        L.gpulz_decompress_workspace_size.argtypes = [u64, u64, ctypes.POINTER(sz)]
         L.gpulz_decompress.restype = ctypes.c_int
         L.gpulz_decompress.argtypes = [vp, u64, vp, u64, vp, vp, vp, sz, vp]
         L.gpulz_decompress_noalloc.restype = ctypes.c_int
@@ -179,9 +185,9 @@ def gpulz_peek_header(header: bytes):
     return n.value, s.value, total.value
 
 
-def gpulz_decompress_workspace_size(stream_bytes: int) -> int:
+def gpulz_decompress_workspace_size(comp_bytes: int, nbytes: int = 0) -> int:
     ws = ctypes.c_size_t(0)
-    st = lib().gpulz_decompress_workspace_size(stream_bytes, ctypes.byref(ws))
+    st = lib().gpulz_decompress_workspace_size(comp_bytes, nbytes, ctypes.byref(ws))
     if st != GPULZ_OK:
         raise GpulzError(st, "gpulz_decompress_workspace_size")
     return ws.value
