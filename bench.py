@@ -52,14 +52,14 @@ HBM_PEAK_GBPS = 8000.0
 # "prep" is the compress call's preparation kernel (look-back descriptors
 # and tickets zeroed); the step is prep + encode.
 ENCODE_COUNTERS = {
-    "sources_sha256": None,
-    "fetch_kib": None, "write_kib": None,
-    "prep_fetch_kib": None, "prep_write_kib": None,
+    "sources_sha256": "1376381409e78c9ba0a7e0355f23d745a087fadda04c77a186e8b53384870056",
+    "fetch_kib": 140671.4, "write_kib": 277038.5,
+    "prep_fetch_kib": 16.0, "prep_write_kib": 128.3,
     "fetch_scale": 2.0, "write_scale": 1.0,
 }
 ENCODE_SOURCES = ("paper_2304_07342_amd/csrc/lz_encode.hip", "paper_2304_07342_amd/csrc/encode_device.h",
-                  "paper_2304_07342_amd/csrc/stream_device.h", "paper_2304_07342_amd/csrc/wave.h",
-                  "paper_2304_07342_amd/csrc/gpulz_internal.h")
+                  "paper_2304_07342_amd/csrc/dense_asm.h", "paper_2304_07342_amd/csrc/stream_device.h",
+                  "paper_2304_07342_amd/csrc/wave.h", "paper_2304_07342_amd/csrc/gpulz_internal.h")
 
 
 def encoder_sources_sha256() -> str:
@@ -290,19 +290,25 @@ def run_small(args):
     print(json.dumps(small_leg(args)), flush=True)
 
 
-# Match-dense inputs at the parameters the autotuner picks for them (1 GiB
-# width sweep): (kind, seed, S, C, W, MIN, waves per chunk).
-DENSE_INPUTS = (("zipf-u8", 201, 1, 2048, 256, 2, 1), ("laplace-u16", 202, 2, 4096, 256, 2, 4))
+# Match-dense inputs: (kind, seed, S, MIN). Chunk size, window and waves per
+# chunk are the autotuner's choice on the first 64 MiB of the same input.
+DENSE_INPUTS = (("zipf-u8", 201, 1, 2), ("laplace-u16", 202, 2, 2))
 
 
-def dense_leg(args, kind, seed, S, C, W, MIN, waves, size):
+def dense_leg(args, kind, seed, S, MIN, size, params=None):
     """One match-dense input: compress GB/s, ratio, the encode kernel's
     average time (HIP events on the call's stream) and its algorithmic
-    compare rate against the ALU compare peak."""
+    compare rate against the ALU compare peak. `params` = (C, W, waves) skips
+    the autotuner."""
     import torch
-    from paper_2304_07342_amd import gpulz, synth
+    from paper_2304_07342_amd import autotune, gpulz, synth
     log(f"dense {kind} {size >> 20} MiB")
     x = torch.from_numpy(synth.POOL_KINDS[kind][1](size, seed)[:size]).to("cuda")
+    tuned = None
+    if params is None:
+        tuned = autotune.tune_width(x[: min(size, 64 << 20)], S, MIN)
+        params = (tuned["chunk_symbols"], tuned["window"], tuned["waves_per_chunk"])
+    C, W, waves = params
     saved = gpulz.gpulz_default_params(S)
     gpulz.gpulz_set_default_params(S, saved[0], saved[1], saved[2], waves)
     try:
@@ -336,7 +342,10 @@ def dense_leg(args, kind, seed, S, C, W, MIN, waves, size):
            "value": round(size / ms / 1e6, 3), "unit": "GB/s", "ms_per_step": round(ms, 4),
            "ratio": round(size / nbytes, 4), "chunk_symbols": C, "window": W, "min_match": MIN,
            "waves_per_chunk": waves, "kernel_avg_ms": kernel_ms,
-           "compare_peak_frac": round(cmp / (enc_ms / 1e3) / 1e12 / ALU_PEAK_TCMP, 4)}
+           "compare_peak_frac": round(cmp / (enc_ms / 1e3) / 1e12 / ALU_PEAK_TCMP, 4),
+           "params_from": "autotuner" if tuned else "given"}
+    if tuned:
+        out["autotune_candidates"] = len(tuned["measurements"])
     del x, comp, d
     torch.cuda.empty_cache()
     return out
@@ -345,8 +354,9 @@ def dense_leg(args, kind, seed, S, C, W, MIN, waves, size):
 def run_dense(args):
     """256 MiB each of Zipf bytes and uint16 Laplace codes, the match-dense
     inputs where the exact search runs at almost every token."""
-    for kind, seed, S, C, W, MIN, waves in DENSE_INPUTS:
-        leg = dense_leg(args, kind, seed, S, C, W, MIN, waves, args.dense_mib << 20)
+    for kind, seed, S, MIN in DENSE_INPUTS:
+        params = tuple(args.dense_params) if args.dense_params else None
+        leg = dense_leg(args, kind, seed, S, MIN, args.dense_mib << 20, params)
         leg["metric"] = "compress GB/s (input) + ratio"
         print(json.dumps(leg), flush=True)
 
@@ -694,6 +704,8 @@ def main():
                              "entropy", "batch", "serve"])
     ap.add_argument("--sweep-bytes", type=int, default=1 << 30)
     ap.add_argument("--dense-mib", type=int, default=256)
+    ap.add_argument("--dense-params", type=int, nargs=3, metavar=("C", "W", "WAVES"),
+                    help="dense workload at these parameters instead of the autotuner's")
     ap.add_argument("--nbufs", type=int, default=4096)
     ap.add_argument("--pool-mib", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -864,8 +876,8 @@ def main():
         torch.cuda.empty_cache()
         print("[bench] config 0: 1 MiB uint16 codes", file=sys.stderr, flush=True)
         result["small"] = small_leg(args)
-        kind, seed, S2, C2, W2, MIN2, waves2 = DENSE_INPUTS[1]
-        result["dense_u16"] = dense_leg(args, kind, seed, S2, C2, W2, MIN2, waves2, 256 << 20)
+        kind, seed, S2, MIN2 = DENSE_INPUTS[1]
+        result["dense_u16"] = dense_leg(args, kind, seed, S2, MIN2, 256 << 20)
         if not args.no_batch:
             print("[bench] config 3: batch of 4096 buffers", file=sys.stderr, flush=True)
             bargs = argparse.Namespace(**vars(args))
