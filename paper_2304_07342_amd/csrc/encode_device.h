@@ -77,7 +77,11 @@ struct ChunkJob {
 
 template <int S> struct Geo {
   static constexpr int V = 16 / S;                  // symbols per 16-byte vector
-  static constexpr uint32_t kBlock = 64u * V;       // positions per wave block
+  // 16-byte vectors per lane in the hit phase: two for 4- and 8-byte symbols
+  // (one window read then serves 2 V positions), one for narrower ones,
+  // whose single vector already holds 8 or 16
+  static constexpr int R = S >= 4 ? 2 : 1;
+  static constexpr uint32_t kBlock = 64u * V * R;   // positions per wave block
 };
 
 // Window columns of the streaming search (1- and 2-byte symbols): 4 / S
@@ -92,20 +96,28 @@ __host__ __device__ constexpr uint32_t pad_for(uint32_t S, uint32_t wc) {
   return (uint32_t)align_up((a > b ? a : b) + 16u, 16);
 }
 
-// LDS layout: [pad | chunk (rounded up to whole 1 KiB blocks) + slack | hit bitmap]
+// LDS layout: [pad | chunk (rounded up to whole hit blocks) + slack | hit bitmap]
 template <int S, int WC>
 __host__ __device__ constexpr uint32_t pad_bytes() {
   return pad_for(S, WC);
 }
 __host__ __device__ constexpr uint64_t chunk_lds_bytes(uint32_t C, uint32_t S) {
-  return align_up((uint64_t)C * S, 1024) + 64;
+  return align_up((uint64_t)C * S, S >= 4 ? 2048 : 1024) + 64;  // whole hit blocks
 }
 __host__ __device__ constexpr uint64_t hit_words(uint32_t C, uint32_t S) {
   return align_up(C, 1024 / S) / 32 + 64;
 }
-// LDS of one chunk encoder with wc window columns.
-__host__ __device__ constexpr uint64_t encode_lds(uint32_t C, uint32_t S, uint32_t wc) {
-  return pad_for(S, wc) + chunk_lds_bytes(C, S) + 4 * hit_words(C, S);
+// Candidate list of a sparse chunk (4- and 8-byte symbols, workgroups of
+// several waves): per wave up to kListPerWave candidate positions and their
+// search results, then one count per wave.
+constexpr uint32_t kListPerWave = 32;
+__host__ __device__ constexpr uint64_t list_lds_bytes(uint32_t S, uint32_t waves) {
+  return S >= 4 && waves > 1 ? 4ull * (2 * kEncodeWaves * kListPerWave + kEncodeWaves) : 0ull;
+}
+// LDS of one chunk encoder with wc window columns and `waves` waves.
+__host__ __device__ constexpr uint64_t encode_lds(uint32_t C, uint32_t S, uint32_t wc,
+                                                  uint32_t waves) {
+  return pad_for(S, wc) + chunk_lds_bytes(C, S) + 4 * hit_words(C, S) + list_lds_bytes(S, waves);
 }
 
 template <int S>
@@ -229,80 +241,183 @@ __device__ __forceinline__ void encode_group(uint32_t cnt, uint32_t desc, uint32
   pay += S * popc64(lm) + 2u * popc64(pm);
 }
 
-// Compares this lane's V symbols x[] with the window vector q (the V symbols
-// that sit V * k positions back) and the vector after it (prev), for the
-// offsets d = V * (k - 1) + j, j = 1 .. jmax.
-template <int S, bool kHead, bool kPartial, int kStep>
-__device__ __forceinline__ void hit_step(const typename SymType<S>::T (&x)[16 / S],
-                                         const uint4& qv, const uint4& prev, uint32_t dk,
-                                         uint32_t jmax, uint32_t pos0, uint64_t (&acc)[16 / S]) {
+// Compares this lane's V R symbols x[] with the window vectors wv[0..R]
+// (wv[0] sits V k positions before the lane's first vector, wv[r] the r-th
+// vector after it), for the offsets d = V (k - 1) + j, j = 1 .. jmax. In the
+// chunk's first W positions (kHead) only offsets d <= p count; 4- and 8-byte
+// symbols need no such mask (the bytes before the chunk hold a symbol that
+// none of the first W symbols equals, see fill_pad_distinct).
+template <int S, bool kHead, bool kPartial, int kStep, int R>
+__device__ __forceinline__ void hit_step(const typename SymType<S>::T (&x)[16 / S * R],
+                                         const uint4 (&wv)[R + 1], uint32_t dk, uint32_t jmax,
+                                         uint32_t base, uint64_t (&acc)[16 / S * R]) {
   using T = typename SymType<S>::T;
   constexpr int V = Geo<S>::V;
-  T q[2 * V];
+  constexpr int VR = V * R;
+  T q[(R + 1) * V];
 #pragma unroll
-  for (int e = 0; e < V; ++e) {
-    q[e] = vec_elem<S>(qv, e);
-    q[V + e] = vec_elem<S>(prev, e);
-  }
+  for (int r = 0; r <= R; ++r)
+#pragma unroll
+    for (int e = 0; e < V; ++e) q[r * V + e] = vec_elem<S>(wv[r], e);
+  static_assert(!kHead || R == 1, "4- and 8-byte symbols run no head variant");
 #pragma unroll
   for (int j = 1; j <= V; ++j) {
     if (kPartial && (uint32_t)j > jmax) break;
 #pragma unroll
-    for (int i = 0; i < V; i += kStep) {
-      if constexpr (kHead) {
-        acc[i] |= ballot((x[i] == q[i + V - j]) & (pos0 + i >= dk + j));
-      } else {
+    for (int i = 0; i < VR; i += kStep) {
+      if constexpr (kHead)
+        acc[i] |= ballot((x[i] == q[i + V - j]) & (base + VR * lane_id() + i >= dk + j));
+      else
         acc[i] |= ballot(x[i] == q[i + V - j]);
-      }
     }
-    // with 8 or 16 positions per lane, keep at most V compare masks live
-    // (more would spill SGPRs); wider symbols schedule better without it
-    if constexpr (S <= 2) __builtin_amdgcn_sched_barrier(0);
+    // with 8 or 16 positions per lane, keep at most V R compare masks live
+    // (more would spill SGPRs); 4 positions schedule better without it
+    if constexpr (VR >= 8) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-// Hit bitmap for one block of 64 * V positions starting at `base`: for every
-// kStep-th position p, bit p is set iff some offset d <= min(W, p) has
-// sym[p - d] == sym[p] (the other bits stay 0).
+// Hit bitmap for one block of 64 V R positions starting at `base` (each lane
+// owns R consecutive 16-byte vectors): for every kStep-th position p, bit p
+// is set iff some offset d <= min(W, p) has sym[p - d] == sym[p] (the other
+// bits stay 0). Step k reads the one vector V k positions back; the R before
+// it come from the previous steps, held in a ring of R + 1 registers whose
+// slot for step k is k mod (R + 1), so the steps are unrolled R + 1 at a time
+// and every ring index is a constant.
 template <int S, bool kHead, int kStep>
 __device__ __forceinline__ void hit_block(const uint4* w4, uint32_t base, uint32_t W,
                                           uint32_t* hits) {
   using T = typename SymType<S>::T;
   constexpr int V = Geo<S>::V;
+  constexpr int R = Geo<S>::R;
+  constexpr int VR = V * R;
   const uint32_t lane = lane_id();
-  const int vbase = (int)(base / V + lane);
-  const uint4 xv = w4[vbase];
-  T x[V];
+  const int vbase = (int)(base / V + R * lane);
+  uint4 ring[R + 1];
+  T x[VR];
+  uint4 x0v = w4[vbase];  // with R = 1: the vector after the current step's
 #pragma unroll
-  for (int i = 0; i < V; ++i) x[i] = vec_elem<S>(xv, i);
-  uint64_t acc[V];
+  for (int m = 0; m < R; ++m) {
+    const uint4 v = m == 0 ? x0v : w4[vbase + m];
+    ring[(R + 1 - m) % (R + 1)] = v;  // the vector m after the lane's first: slot -m
 #pragma unroll
-  for (int i = 0; i < V; ++i) acc[i] = 0;
-  const uint32_t pos0 = base + V * lane;  // this lane's first position
-  const uint32_t kfull = W / V;           // steps whose V offsets are all <= W
-  uint4 prev = xv;
+    for (int e = 0; e < V; ++e) x[m * V + e] = vec_elem<S>(v, e);
+  }
+  uint64_t acc[VR];
+#pragma unroll
+  for (int i = 0; i < VR; ++i) acc[i] = 0;
+  const uint32_t pos0 = base + VR * lane;  // this lane's first position
+  const uint32_t kfull = W / V;            // steps whose V offsets are all <= W
   uint32_t k = 1;
-  for (; k + 1 <= kfull; k += 2) {
-    const uint4 q1 = w4[vbase - (int)k];
-    const uint4 q2 = w4[vbase - (int)k - 1];
-    hit_step<S, kHead, false, kStep>(x, q1, prev, V * (k - 1), V, pos0, acc);
-    hit_step<S, kHead, false, kStep>(x, q2, q1, V * k, V, pos0, acc);
-    prev = q2;
-  }
-  if (k <= kfull) {
-    const uint4 q1 = w4[vbase - (int)k];
-    hit_step<S, kHead, false, kStep>(x, q1, prev, V * (k - 1), V, pos0, acc);
-    prev = q1;
-    ++k;
-  }
-  if (W % V) {
-    const uint4 q1 = w4[vbase - (int)k];
-    hit_step<S, kHead, true, kStep>(x, q1, prev, V * (k - 1), W % V, pos0, acc);
+  if constexpr (R == 1) {
+    // two steps per round: ring slot 1 for odd k, 0 for even k
+    for (; k + 1 <= kfull; k += 2) {
+      ring[1] = w4[vbase - (int)k];
+      ring[0] = w4[vbase - (int)k - 1];
+      const uint4 w1[2] = {ring[1], x0v}, w2[2] = {ring[0], ring[1]};
+      hit_step<S, kHead, false, kStep, R>(x, w1, V * (k - 1), V, base, acc);
+      hit_step<S, kHead, false, kStep, R>(x, w2, V * k, V, base, acc);
+      x0v = ring[0];
+    }
+    if (k <= kfull) {
+      const uint4 q1 = w4[vbase - (int)k];
+      const uint4 w1[2] = {q1, x0v};
+      hit_step<S, kHead, false, kStep, R>(x, w1, V * (k - 1), V, base, acc);
+      x0v = q1;
+      ++k;
+    }
+    if (W % V) {
+      const uint4 w1[2] = {w4[vbase - (int)k], x0v};
+      hit_step<S, kHead, true, kStep, R>(x, w1, V * (k - 1), W % V, base, acc);
+    }
+  } else {
+    for (; k + R <= kfull; k += R + 1) {
+      uint4 nv[R + 1];
+#pragma unroll
+      for (int u = 0; u <= R; ++u) nv[u] = w4[vbase - (int)(k + u)];
+#pragma unroll
+      for (int u = 0; u <= R; ++u) {
+        ring[(1 + u) % (R + 1)] = nv[u];
+        uint4 wv[R + 1];
+#pragma unroll
+        for (int r = 0; r <= R; ++r) wv[r] = ring[(1 + u - r + 2 * (R + 1)) % (R + 1)];
+        hit_step<S, kHead, false, kStep, R>(x, wv, V * (k + u - 1), V, base, acc);
+      }
+    }
+    // at most R full steps remain, then the partial one (W % V offsets)
+#pragma unroll
+    for (int u = 0; u <= R; ++u) {
+      const uint32_t kk = k + u;
+      if (kk <= kfull || (kk == kfull + 1 && W % V)) {
+        ring[(1 + u) % (R + 1)] = w4[vbase - (int)kk];
+        uint4 wv[R + 1];
+#pragma unroll
+        for (int r = 0; r <= R; ++r) wv[r] = ring[(1 + u - r + 2 * (R + 1)) % (R + 1)];
+        if (kk <= kfull)
+          hit_step<S, kHead, false, kStep, R>(x, wv, V * (kk - 1), V, base, acc);
+        else
+          hit_step<S, kHead, true, kStep, R>(x, wv, V * (kk - 1), W % V, base, acc);
+      }
+    }
   }
   uint32_t bits = 0;
 #pragma unroll
-  for (int i = 0; i < V; i += kStep) bits |= (uint32_t)((acc[i] >> lane) & 1u) << i;
+  for (int i = 0; i < VR; i += kStep) bits |= (uint32_t)((acc[i] >> lane) & 1u) << i;
   if (bits) atomicOr(&hits[pos0 >> 5], bits << (pos0 & 31u));
+}
+
+// 4- and 8-byte symbols: fills the `pad` bytes before the staged chunk with
+// one symbol value that none of the chunk's first `lim` = min(W, c) symbols
+// equals, so that compares reaching before the chunk never hit and the hit
+// phase needs no per-offset mask there. At most lim <= 256 values are taken,
+// so counting up from a fixed pattern finds one within lim + 1 rounds. Run
+// by the one wave that builds block 0 (the only block whose window reaches
+// before the chunk); the stage must be visible to it.
+template <int S>
+__device__ __forceinline__ void fill_pad_distinct(uint8_t* stage, uint32_t pad, uint32_t lim) {
+  using T = typename SymType<S>::T;
+  const T* sym = reinterpret_cast<const T*>(stage);
+  const uint32_t lane = lane_id();
+  T own[4];
+  bool in[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    in[t] = lane + 64u * t < lim;
+    own[t] = in[t] ? sym[lane + 64u * t] : (T)0;
+  }
+  T v = (T)0x9E3779B97F4A7C15ull;
+  for (;;) {
+    bool eq = false;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) eq |= in[t] && own[t] == v;
+    if (!ballot(eq)) break;
+    ++v;
+  }
+  T* before = reinterpret_cast<T*>(stage - pad);
+  for (uint32_t k = lane; k < pad / S; k += 64) before[k] = v;
+  wave_sync();
+}
+
+// Hit blocks b0, b0 + step, ... below nblocks of the staged chunk.
+template <int S, int WC>
+__device__ __forceinline__ void build_hits(uint8_t* stage, uint32_t b0, uint32_t nblocks,
+                                           uint32_t step, uint32_t W, uint32_t c, bool sampled,
+                                           uint32_t* hits) {
+  constexpr uint32_t kBlock = Geo<S>::kBlock;
+  const uint4* w4 = reinterpret_cast<const uint4*>(stage);
+  for (uint32_t b = b0; b < nblocks; b += step) {
+    const uint32_t base = b * kBlock;
+    if constexpr (Geo<S>::R > 1) {
+      if (b == 0) fill_pad_distinct<S>(stage, pad_bytes<S, WC>(), min(W, c));
+      if (sampled) hit_block<S, false, 2>(w4, base, W, hits);
+      else hit_block<S, false, 1>(w4, base, W, hits);
+    } else if (sampled) {
+      if (base >= W) hit_block<S, false, 2>(w4, base, W, hits);
+      else hit_block<S, true, 2>(w4, base, W, hits);
+    } else {
+      if (base >= W) hit_block<S, false, 1>(w4, base, W, hits);
+      else hit_block<S, true, 1>(w4, base, W, hits);
+    }
+  }
 }
 
 // Word w of the candidate bitmap: the hit bitmap itself, or, when only even
@@ -323,7 +438,19 @@ __device__ __forceinline__ void stage_chunk(const ChunkJob& job, uint8_t* stage)
   const uint32_t nbytes = job.c * S;
   if (((uintptr_t)job.src & 15) == 0) {
     const uint32_t nw = (nbytes + 15) / 16;
-    for (uint32_t k = tid; k < nw; k += blockDim.x) {
+    // words wholly inside the input, four per thread in flight
+    const uint32_t full = (uint32_t)min<uint64_t>(nw, job.src_avail / 16);
+    const uint32_t step = blockDim.x;
+    uint32_t k = tid;
+    for (; k + 3 * step < full; k += 4 * step) {
+      uint4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        v[u] = *reinterpret_cast<const uint4*>(job.src + 16ull * (k + u * step));
+#pragma unroll
+      for (int u = 0; u < 4; ++u) *reinterpret_cast<uint4*>(stage + 16 * (k + u * step)) = v[u];
+    }
+    for (; k < nw; k += step) {
       const uint64_t g = 16ull * k;
       if (g + 16 <= job.src_avail) {
         *reinterpret_cast<uint4*>(stage + 16 * k) = *reinterpret_cast<const uint4*>(job.src + g);
@@ -367,6 +494,43 @@ struct CandCursor {
       }
       w = hw0 + 64;
       if (w * 32u >= c) return c;
+    }
+  }
+};
+
+// Cursor over the candidate list of a sparse chunk: the sub-lists of the
+// waves in order (each sorted, each over a later range of positions), one
+// sub-list cached per lane. next() returns the first candidate at or after p
+// (c if none) and its search result; p never decreases between calls.
+struct ListCursor {
+  const uint32_t* pos;
+  const uint32_t* key;
+  const uint32_t* cnt;
+  uint32_t w, nw, n, ch, ck;
+  __device__ __forceinline__ void load() {
+    const uint32_t lane = lane_id();
+    n = cnt[w];
+    ch = lane < n ? pos[w * kListPerWave + lane] : 0u;
+    ck = lane < n ? key[w * kListPerWave + lane] : 0u;
+  }
+  __device__ __forceinline__ void init(const uint32_t* list, uint32_t waves) {
+    pos = list;
+    key = list + kEncodeWaves * kListPerWave;
+    cnt = key + kEncodeWaves * kListPerWave;
+    w = 0;
+    nw = waves;
+    load();
+  }
+  __device__ __forceinline__ uint32_t next(uint32_t p, uint32_t c, uint32_t& k) {
+    for (;;) {
+      const uint64_t m = ballot(lane_id() < n && ch >= p);
+      if (m) {
+        const uint32_t j = (uint32_t)__builtin_ctzll(m);
+        k = readlane(ck, j);
+        return readlane(ch, j);
+      }
+      if (++w >= nw) return c;
+      load();
     }
   }
 };
@@ -1144,6 +1308,64 @@ __device__ __forceinline__ void encode_group_out(uint32_t cnt, uint32_t desc, ui
   if (lane < 8 && 8u * group + lane < F) rec[8u * group + lane] = (uint8_t)(pm >> (8u * lane));
 }
 
+// Sparse chunks in workgroups of several waves: the exact search at a
+// candidate depends on its position only, not on the parse, so the waves
+// run the searches of all candidates before the parse, each over its share
+// of the bitmap words, into the candidate list (positions in order, one
+// sub-list per wave). All waves call this after the hit bitmap is complete;
+// it returns, uniformly over the workgroup, whether every sub-list fit (else
+// the parse searches as it goes). Candidates the parse later jumps over are
+// searched for nothing, which is why this is for sparse chunks only.
+template <int S, int WC>
+__device__ bool build_list(const uint8_t* stage, const uint32_t* hits, uint32_t nhw,
+                           bool sampled, const ChunkJob& job, const uint64_t (&wmask)[WC],
+                           uint32_t* list, uint32_t wave, uint32_t nwaves) {
+  using T = typename SymType<S>::T;
+  const uint32_t lane = lane_id();
+  const uint32_t c = job.c;
+  uint32_t* lpos = list + wave * kListPerWave;
+  uint32_t* lkey = list + kEncodeWaves * kListPerWave + wave * kListPerWave;
+  uint32_t* cnt = list + 2 * kEncodeWaves * kListPerWave;
+  const uint32_t nwords = (c + 31) / 32;
+  const uint32_t w0 = wave * nwords / nwaves, w1 = (wave + 1) * nwords / nwaves;
+  uint32_t n = 0;
+  bool over = false;
+  for (uint32_t wb = w0; wb < w1; wb += 64) {
+    const uint32_t gw = wb + lane;
+    uint32_t word = gw < w1 ? cand_word(hits, gw, nhw, sampled) : 0u;
+    if (gw * 32u + 32u > c) word &= gw * 32u >= c ? 0u : (1u << (c - gw * 32u)) - 1u;
+    const uint32_t pc = (uint32_t)__popc(word);
+    const uint32_t incl = wave_incl_scan(pc);
+    const uint32_t tot = readlane(incl, 63);
+    if (n + tot > kListPerWave) {
+      over = true;
+      break;
+    }
+    uint32_t o = n + incl - pc;
+    while (word) {
+      lpos[o++] = gw * 32u + (uint32_t)__ffs(word) - 1u;
+      word &= word - 1u;
+    }
+    n += tot;
+  }
+  wave_sync();
+  if (lane == 0) cnt[wave] = over ? ~0u : n;
+  if (!over) {
+    const T* win = reinterpret_cast<const T*>(stage);
+    StreamMatchFor<S, WC> sm;
+    sm.init(stage, job.W, lane);
+    for (uint32_t i = 0; i < n; ++i) {
+      const uint32_t h = __builtin_amdgcn_readfirstlane(lpos[i]);
+      const uint32_t key = find_token<S, WC>(sm, win, h, c, job.W, job.MIN, wmask, lane);
+      if (lane == 0) lkey[i] = key;
+    }
+  }
+  __syncthreads();
+  bool ok = true;
+  for (uint32_t w = 0; w < nwaves; ++w) ok &= cnt[w] != ~0u;
+  return ok;
+}
+
 // Encodes one chunk. Every wave of the workgroup stages the chunk and builds
 // the hit bitmap; waves other than 0 return after that, wave 0 parses and
 // encodes.
@@ -1203,25 +1425,23 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
         b0 = dense ? nblocks : 1;
       }
     }
-    for (uint32_t b = b0; b < nblocks; b += nwaves) {
-      const uint32_t base = b * kBlock;
-      if (sampled) {
-        if (base >= job.W) hit_block<S, false, 2>(w4, base, job.W, hits);
-        else hit_block<S, true, 2>(w4, base, job.W, hits);
-      } else {
-        if (base >= job.W) hit_block<S, false, 1>(w4, base, job.W, hits);
-        else hit_block<S, true, 1>(w4, base, job.W, hits);
-      }
-    }
+    build_hits<S, WC>(stage, b0, nblocks, nwaves, job.W, c, sampled, hits);
   }
   __syncthreads();
-  if (wave != 0) return;
-
-  // ---- parse + encode: wave 0
   const T* win = reinterpret_cast<const T*>(stage);
   uint64_t wmask[WC];
 #pragma unroll
   for (int col = 0; col < WC; ++col) wmask[col] = ballot(64u * col + lane + 1u <= job.W);
+  // the candidate list is taken for 4- and 8-byte symbols (1- and 2-byte
+  // chunks with sparse candidates are rare and keep the search in the parse)
+  uint32_t* list = hits + nhw;
+  bool listed = false;
+  if constexpr (S >= 4)
+    listed = nwaves > 1 && build_list<S, WC>(stage, hits, nhw, sampled, job, wmask, list, wave,
+                                             nwaves);
+  if (wave != 0) return;
+
+  // ---- parse + encode: wave 0
 
   uint8_t* slot = job.slot;
   uint32_t ntok = 0, pay = 0, desc = 0, g0 = kNoGroup;
@@ -1238,11 +1458,14 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
     }
   }
   CandCursor cc;
-  cc.init(hits, nhw, sampled);
+  ListCursor lc;
+  if (listed) lc.init(list, nwaves);
+  else cc.init(hits, nhw, sampled);
   StreamMatchFor<S, WC> sm;
   sm.init(stage, job.W, lane);
   while (p < c) {
-    const uint32_t h = cc.next(p, c, hits, nhw, sampled);
+    uint32_t lkey = 0;
+    const uint32_t h = listed ? lc.next(p, c, lkey) : cc.next(p, c, hits, nhw, sampled);
     // literals for [p, h); on the single-pass path, whole all-literal groups
     // before the first pointer are only counted
     if constexpr (kSinglePass) {
@@ -1264,7 +1487,8 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
     }
     if (h >= c) break;
 
-    const uint32_t key = find_token<S, WC>(sm, win, h, c, job.W, job.MIN, wmask, lane);
+    const uint32_t key =
+        listed ? lkey : find_token<S, WC>(sm, win, h, c, job.W, job.MIN, wmask, lane);
     uint32_t val;
     if (key) {
       val = 1u | ((key >> 9) << 1) | ((key & 0xFFu) << 9);
@@ -1304,7 +1528,7 @@ __host__ __device__ constexpr uint64_t spec_bitmap_words(uint32_t C) { return (C
 // and pointer bitmaps | segment ends | meeting points]
 template <int S, int WC>
 __host__ __device__ constexpr uint64_t spec_lds_bytes(uint32_t C) {
-  return encode_lds(C, S, WC) + 4 * 4 * spec_bitmap_words(C) + align_up(2ull * C, 16) +
+  return encode_lds(C, S, WC, 1) + 4 * 4 * spec_bitmap_words(C) + align_up(2ull * C, 16) +
          2 * 4 * (spec_bitmap_words(C) + 1) + 2 * 4 * kSpecWaves;
 }
 
@@ -1362,20 +1586,7 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
   for (uint32_t k = tid; k < 4 * tw; k += blockDim.x) tok[k] = 0;
   __syncthreads();
   const bool sampled = job.MIN >= 2;
-  {
-    const uint4* w4 = reinterpret_cast<const uint4*>(stage);
-    const uint32_t nblocks = (c + kBlock - 1) / kBlock;
-    for (uint32_t b = wave; b < nblocks; b += nwaves) {
-      const uint32_t base = b * kBlock;
-      if (sampled) {
-        if (base >= job.W) hit_block<S, false, 2>(w4, base, job.W, hits);
-        else hit_block<S, true, 2>(w4, base, job.W, hits);
-      } else {
-        if (base >= job.W) hit_block<S, false, 1>(w4, base, job.W, hits);
-        else hit_block<S, true, 1>(w4, base, job.W, hits);
-      }
-    }
-  }
+  build_hits<S, WC>(stage, wave, (c + kBlock - 1) / kBlock, nwaves, job.W, c, sampled, hits);
   __syncthreads();
 
   const T* win = reinterpret_cast<const T*>(stage);
@@ -1688,8 +1899,8 @@ __device__ void encode_chunk_scan(const ChunkJob& job, uint8_t* lds) {
 }
 
 template <int S, int WC>
-__host__ __device__ constexpr size_t lds_bytes(uint32_t C) {
-  return encode_lds(C, S, WC);
+__host__ __device__ constexpr size_t lds_bytes(uint32_t C, uint32_t waves) {
+  return encode_lds(C, S, WC, waves);
 }
 
 }  // namespace enc

@@ -97,7 +97,7 @@ hipError_t launch_fused_prep(const FusedArgs& a, hipStream_t s);
 hipError_t launch_fused_encode(const FusedArgs& a, uint32_t waves, hipStream_t s);
 
 
-size_t encode_lds_bytes(uint32_t C, uint32_t S, uint32_t W);
+size_t encode_lds_bytes(uint32_t C, uint32_t S, uint32_t W, uint32_t waves);
 size_t encode_scan_lds_bytes(uint32_t C, uint32_t S);
 
 // ---- decompress -------------------------------------------------------------

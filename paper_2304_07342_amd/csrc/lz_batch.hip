@@ -331,7 +331,7 @@ int device_cus() {
 template <int S, uint32_t WI, int WC>
 hipError_t launch_width_wc(const BatchEncArgs& a, hipStream_t s) {
   const uint32_t threads = 64 * a.wp.waves[WI];
-  const size_t lds = encode_lds_bytes(a.wp.C[WI], S, a.wp.W[WI]);
+  const size_t lds = encode_lds_bytes(a.wp.C[WI], S, a.wp.W[WI], a.wp.waves[WI]);
   int per_cu = 0;
   hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(
       &per_cu, batch_encode_kernel<S, WI, WC>, threads, lds);

@@ -105,7 +105,7 @@ hipError_t launch_sw(const FusedArgs& a, uint32_t waves, hipStream_t s) {
                        dim3(64 * enc::kSpecWaves), spec_lds, s, a);
     return hipGetLastError();
   }
-  const size_t lds = enc::lds_bytes<S, WC>(a.C);
+  const size_t lds = enc::lds_bytes<S, WC>(a.C, waves);
   hipLaunchKernelGGL((encode_kernel<S, WC>), dim3((uint32_t)a.nchunks), dim3(64 * waves), lds, s, a);
   return hipGetLastError();
 }
@@ -130,8 +130,8 @@ hipError_t launch_s(const FusedArgs& a, uint32_t waves, hipStream_t s) {
 
 size_t encode_scan_lds_bytes(uint32_t C, uint32_t S) { return enc::scan_lds_bytes(C, S); }
 
-size_t encode_lds_bytes(uint32_t C, uint32_t S, uint32_t W) {
-  return enc::encode_lds(C, S, (W + 63) / 64);
+size_t encode_lds_bytes(uint32_t C, uint32_t S, uint32_t W, uint32_t waves) {
+  return enc::encode_lds(C, S, (W + 63) / 64, waves);
 }
 
 hipError_t launch_fused_prep(const FusedArgs& a, hipStream_t s) {
