@@ -501,7 +501,10 @@ struct CandCursor {
 // Cursor over the candidate list of a sparse chunk: the sub-lists of the
 // waves in order (each sorted, each over a later range of positions), one
 // sub-list cached per lane. next() returns the first candidate at or after p
-// (c if none) and its search result; p never decreases between calls.
+// whose search found a match (c if none) and that result; p never decreases
+// between calls. Candidates without a match are skipped: the greedy parse
+// takes a literal at every position up to the next match, candidate or not,
+// so those positions join the literal run before it.
 struct ListCursor {
   const uint32_t* pos;
   const uint32_t* key;
@@ -523,7 +526,7 @@ struct ListCursor {
   }
   __device__ __forceinline__ uint32_t next(uint32_t p, uint32_t c, uint32_t& k) {
     for (;;) {
-      const uint64_t m = ballot(lane_id() < n && ch >= p);
+      const uint64_t m = ballot(lane_id() < n && ch >= p && ck != 0u);
       if (m) {
         const uint32_t j = (uint32_t)__builtin_ctzll(m);
         k = readlane(ck, j);
