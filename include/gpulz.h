@@ -146,6 +146,53 @@ gpulz_status gpulz_compress_policy(const void* d_in, uint64_t nbytes, uint32_t s
 gpulz_status gpulz_peek_header(const void* h_header, size_t header_bytes, uint64_t* nbytes,
                                uint32_t* symbol_bytes, uint64_t* stream_bytes);
 
+/* ---- stream layout, for callers that assemble or split streams ---------
+ * Data blocks (section 3.3.1): an input too large for device memory is
+ * compressed block by block, each block a whole number of chunks. Since
+ * chunks are independent, a block's table entries and records are exactly
+ * those of the whole input at its chunk and record bases, so one stream is
+ * assembled from the blocks' streams with the entry points below (and split
+ * into per-block streams for decompression the same way). */
+
+/* Fields of a stream header (the layout above). */
+typedef struct {
+  uint64_t nbytes;        /* n: decompressed bytes */
+  uint64_t chunks;        /* N */
+  uint64_t stream_bytes;  /* total stream bytes */
+  uint32_t symbol_bytes, chunk_symbols, window, min_match, match_policy;
+  uint32_t tail_bytes;    /* r = n mod S */
+  uint8_t tail[8];        /* the last r input bytes */
+} gpulz_stream_info;
+
+/* Byte offset of chunk i's table entry in a stream; with i = N, the offset
+ * of chunk 0's record. Host-only. */
+uint64_t gpulz_table_offset(uint64_t chunk);
+
+/* Writes the 64-byte header of a stream with these fields into h_header
+ * (host memory, 64 bytes); h_tail holds the n mod S bytes after the last
+ * whole symbol (may be NULL when there are none). The chunk count is
+ * derived from n, S and C. GPULZ_ERR_INVALID_ARG for parameters that
+ * gpulz_compress rejects, a match policy other than 0 or 1, or a stream
+ * size below 64 + 8N. Host-only. */
+gpulz_status gpulz_write_header(void* h_header, uint64_t nbytes, uint32_t symbol_bytes,
+                                uint32_t chunk_symbols, uint32_t window, uint32_t min_match,
+                                uint32_t match_policy, uint64_t stream_bytes, const void* h_tail);
+
+/* Reads every field of a header from a host copy of its first 64 bytes and
+ * checks them as the decoder does (magic, version, parameter ranges, N from
+ * n, S and C, a stream size of at least 64 + 8N, zero reserved bytes);
+ * GPULZ_ERR_CORRUPT otherwise. Host-only. */
+gpulz_status gpulz_read_header(const void* h_header, size_t header_bytes, gpulz_stream_info* info);
+
+/* Record offsets from a stream's table (section 3.2.2, the prefix sum over
+ * chunk sizes): d_table holds `chunks` table entries (8 bytes each, 4-byte
+ * aligned, device memory), and d_offsets (device, chunks + 1 u64) receives
+ * offsets[i] = F_0 + P_0 + ... + F_{i-1} + P_{i-1}, the offset of chunk i's
+ * record from chunk 0's, and offsets[chunks] = all record bytes. One
+ * workgroup, asynchronous on `stream`; no workspace. */
+gpulz_status gpulz_record_offsets(const void* d_table, uint64_t chunks, uint64_t* d_offsets,
+                                  hipStream_t stream);
+
 /* Workspace bytes gpulz_decompress needs for a stream of `comp_bytes` whose
  * decompressed size is `nbytes` (0 if not known). The size is that of the
  * most chunks a stream of comp_bytes can hold (the decoder rejects a header

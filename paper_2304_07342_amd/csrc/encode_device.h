@@ -1228,7 +1228,7 @@ __device__ inline void finish_stream(const ChunkJob& job, uint64_t excl, uint64_
   }
   if (fits && lane < kHeaderBytes)
     job.out[lane] = stream::header_byte(lane, job.nbytes, job.S, job.C, job.W, job.MIN, job.policy,
-                                        job.N, total, job.in);
+                                        job.N, total, job.in + job.nbytes / job.S * job.S);
 }
 
 // Parse-side handling of a finished group of up to 64 tokens. Two-pass

@@ -10,6 +10,7 @@
 
 #include "gpulz_internal.h"
 #include "huff_internal.h"
+#include "stream_device.h"
 
 using namespace gpulz;
 
@@ -151,7 +152,7 @@ BatchDecLayout batch_dec_layout(uint64_t nbufs, uint64_t max_total) {
 
 extern "C" {
 
-uint32_t gpulz_abi_version(void) { return 101; }
+uint32_t gpulz_abi_version(void) { return 102; }
 
 const char* gpulz_status_string(gpulz_status status) {
   switch (status) {
@@ -269,6 +270,68 @@ gpulz_status gpulz_peek_header(const void* h_header, size_t header_bytes, uint64
   if (symbol_bytes) *symbol_bytes = h[6];
   if (stream_bytes) *stream_bytes = total;
   return GPULZ_OK;
+}
+
+uint64_t gpulz_table_offset(uint64_t chunk) { return kHeaderBytes + 8 * chunk; }
+
+gpulz_status gpulz_write_header(void* h_header, uint64_t nbytes, uint32_t S, uint32_t C, uint32_t W,
+                                uint32_t MIN, uint32_t policy, uint64_t stream_bytes,
+                                const void* h_tail) {
+  if (!h_header || !valid_params(S, C, W, MIN) || policy > 1) return GPULZ_ERR_INVALID_ARG;
+  const uint64_t N = num_chunks(nbytes, S, C);
+  const uint32_t r = (uint32_t)(nbytes % S);
+  if (stream_bytes < kHeaderBytes + 8 * N || (r && !h_tail)) return GPULZ_ERR_INVALID_ARG;
+  uint8_t* h = static_cast<uint8_t*>(h_header);
+  const uint8_t* tail = static_cast<const uint8_t*>(h_tail);
+  for (uint32_t b = 0; b < kHeaderBytes; ++b)
+    h[b] = stream::header_byte(b, nbytes, S, C, W, MIN, policy, N, stream_bytes, tail);
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_read_header(const void* h_header, size_t header_bytes, gpulz_stream_info* info) {
+  if (!h_header || !info || header_bytes < kHeaderBytes) return GPULZ_ERR_INVALID_ARG;
+  const uint8_t* h = static_cast<const uint8_t*>(h_header);
+  auto u64 = [&](int at) {
+    uint64_t v = 0;
+    for (int k = 7; k >= 0; --k) v = (v << 8) | h[at + k];
+    return v;
+  };
+  gpulz_stream_info f{};
+  f.symbol_bytes = h[6];
+  f.match_policy = h[7];
+  f.chunk_symbols = (uint32_t)h[8] | ((uint32_t)h[9] << 8) | ((uint32_t)h[10] << 16) |
+                    ((uint32_t)h[11] << 24);
+  f.window = (uint32_t)h[12] | ((uint32_t)h[13] << 8);
+  f.min_match = h[14];
+  f.nbytes = u64(16);
+  f.chunks = u64(24);
+  f.stream_bytes = u64(32);
+  f.tail_bytes = h[40];
+  bool ok = memcmp(h, "GLZ1", 4) == 0 && h[4] == 1 && h[5] == 0 && f.match_policy <= 1 &&
+            h[15] == kMaxMatch &&
+            valid_params(f.symbol_bytes, f.chunk_symbols, f.window, f.min_match);
+  if (ok) {
+    ok = f.tail_bytes == f.nbytes % f.symbol_bytes &&
+         f.chunks == num_chunks(f.nbytes, f.symbol_bytes, f.chunk_symbols) &&
+         f.chunks <= decode_max_chunks(f.stream_bytes) &&
+         f.stream_bytes >= kHeaderBytes + 8 * f.chunks;
+    for (int k = 41; k < 48; ++k) ok = ok && h[k] == 0;
+    for (uint32_t k = 48 + f.tail_bytes; k < kHeaderBytes; ++k) ok = ok && h[k] == 0;
+  }
+  if (!ok) return GPULZ_ERR_CORRUPT;
+  for (uint32_t k = 0; k < f.tail_bytes; ++k) f.tail[k] = h[48 + k];
+  *info = f;
+  return GPULZ_OK;
+}
+
+gpulz_status gpulz_record_offsets(const void* d_table, uint64_t chunks, uint64_t* d_offsets,
+                                  hipStream_t stream) {
+  if (!d_offsets || !aligned(d_offsets, 8) || (chunks && (!d_table || !aligned(d_table, 4))))
+    return GPULZ_ERR_INVALID_ARG;
+  clear_stale_hip_error();
+  const hipError_t err = launch_record_offsets(static_cast<const uint32_t*>(d_table), chunks,
+                                               d_offsets, stream);
+  return err != hipSuccess ? hip_failed(err, "record offsets launch") : GPULZ_OK;
 }
 
 gpulz_status gpulz_decompress_workspace_size(uint64_t comp_bytes, uint64_t nbytes,

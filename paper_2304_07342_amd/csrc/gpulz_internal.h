@@ -141,6 +141,9 @@ struct DecodeArgs {
 };
 
 hipError_t launch_decode_prepare(const DecodePrepArgs& a, hipStream_t s);
+// offsets[i] = sum of table[2k] + table[2k+1] over k < i, for i = 0 .. chunks
+hipError_t launch_record_offsets(const uint32_t* table, uint64_t chunks, uint64_t* offsets,
+                                 hipStream_t s);
 hipError_t launch_decode_chunks(const DecodeArgs& a, hipStream_t s);
 
 // ---- batches ----------------------------------------------------------------

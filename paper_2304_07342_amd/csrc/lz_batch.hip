@@ -192,7 +192,8 @@ __global__ __launch_bounds__(1024) void batch_enc_scan_kernel(BatchEncArgs a) {
   const bool fits = total <= a.out_caps[b];
   if (threadIdx.x < kHeaderBytes && fits) {
     static_cast<uint8_t*>(a.out_ptrs[b])[threadIdx.x] = stream::header_byte(
-        threadIdx.x, e.n, e.S, e.C, e.W, e.MIN, 0, e.N, total, static_cast<const uint8_t*>(a.in_ptrs[b]));
+        threadIdx.x, e.n, e.S, e.C, e.W, e.MIN, 0, e.N, total,
+        static_cast<const uint8_t*>(a.in_ptrs[b]) + e.n / e.S * e.S);
   }
   __syncthreads();
   if (threadIdx.x == 0) {

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void prep_kernel(FusedArgs a) {
     }
     if (fits && threadIdx.x < kHeaderBytes)
       a.out[threadIdx.x] = stream::header_byte(threadIdx.x, a.nbytes, a.S, a.C, a.W, a.MIN,
-                                               a.policy, 0, total, a.in);
+                                               a.policy, 0, total, a.in + a.nbytes / a.S * a.S);
   }
 }
 

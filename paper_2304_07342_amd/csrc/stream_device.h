@@ -7,10 +7,12 @@
 namespace gpulz {
 namespace stream {
 
-// Byte b (0..63) of the stream header.
-__device__ inline uint8_t header_byte(uint32_t b, uint64_t n, uint32_t S, uint32_t C, uint32_t W,
-                                      uint32_t MIN, uint32_t policy, uint64_t N, uint64_t total,
-                                      const uint8_t* in) {
+// Byte b (0..63) of the stream header; `tail` holds the n mod S bytes after
+// the last whole symbol. The one definition of the header layout, used by
+// the kernels and by the host entry point gpulz_write_header.
+__host__ __device__ inline uint8_t header_byte(uint32_t b, uint64_t n, uint32_t S, uint32_t C,
+                                               uint32_t W, uint32_t MIN, uint32_t policy,
+                                               uint64_t N, uint64_t total, const uint8_t* tail) {
   const uint32_t r = (uint32_t)(n % S);
   switch (b) {
     case 0: return 'G';
@@ -30,7 +32,7 @@ __device__ inline uint8_t header_byte(uint32_t b, uint64_t n, uint32_t S, uint32
   if (b >= 16 && b < 24) return (uint8_t)(n >> (8 * (b - 16)));
   if (b >= 24 && b < 32) return (uint8_t)(N >> (8 * (b - 24)));
   if (b >= 32 && b < 40) return (uint8_t)(total >> (8 * (b - 32)));
-  if (b >= 48 && b < 48 + r) return in[n - r + (b - 48)];
+  if (b >= 48 && b < 48 + r) return tail[b - 48];
   return 0;
 }
 

@@ -32,6 +32,7 @@ EXPORTS = (
     "gpulz_decompress_batch_workspace_size", "gpulz_decompress_batch", "gpulz_profile_enable",
     "gpulz_profile_read", "gpulz_huff_compress_bound", "gpulz_huff_compress_workspace_size",
     "gpulz_huff_compress", "gpulz_huff_decompress_workspace_size", "gpulz_huff_decompress",
+    "gpulz_table_offset", "gpulz_write_header", "gpulz_read_header", "gpulz_record_offsets",
 )
 KERNEL_NAMES = ("encode", "prep", "unused", "decode_prepare", "decode", "compress_batch",
                 "decompress_batch", "huff_compress", "huff_decompress")
@@ -55,6 +56,15 @@ def params_array(by_width=None):
         p = tuple(p) + (0,) * (4 - len(p))
         arr[w] = Params(*p)
     return arr
+
+
+class StreamInfo(ctypes.Structure):
+    """gpulz_stream_info: the fields of a stream header."""
+    _fields_ = [("nbytes", ctypes.c_uint64), ("chunks", ctypes.c_uint64),
+                ("stream_bytes", ctypes.c_uint64), ("symbol_bytes", ctypes.c_uint32),
+                ("chunk_symbols", ctypes.c_uint32), ("window", ctypes.c_uint32),
+                ("min_match", ctypes.c_uint32), ("match_policy", ctypes.c_uint32),
+                ("tail_bytes", ctypes.c_uint32), ("tail", ctypes.c_uint8 * 8)]
 
 
 class GpulzError(RuntimeError):
@@ -131,6 +141,14 @@ def lib() -> ctypes.CDLL:
         L.gpulz_huff_decompress_workspace_size.argtypes = [u64, ctypes.POINTER(sz)]
         L.gpulz_huff_decompress.restype = ctypes.c_int
         L.gpulz_huff_decompress.argtypes = [vp, u64, vp, u64, vp, vp, vp, sz, vp]
+        L.gpulz_table_offset.restype = u64
+        L.gpulz_table_offset.argtypes = [u64]
+        L.gpulz_write_header.restype = ctypes.c_int
+        L.gpulz_write_header.argtypes = [vp, u64, u32, u32, u32, u32, u32, u64, ctypes.c_char_p]
+        L.gpulz_read_header.restype = ctypes.c_int
+        L.gpulz_read_header.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(StreamInfo)]
+        L.gpulz_record_offsets.restype = ctypes.c_int
+        L.gpulz_record_offsets.argtypes = [vp, u64, vp, vp]
         _lib = L
     return _lib
 
@@ -183,6 +201,34 @@ def gpulz_peek_header(header: bytes):
     if st != GPULZ_OK:
         raise GpulzError(st, "gpulz_peek_header")
     return n.value, s.value, total.value
+
+
+def gpulz_table_offset(chunk: int) -> int:
+    return lib().gpulz_table_offset(chunk)
+
+
+def gpulz_write_header(nbytes: int, symbol_bytes: int, chunk_symbols: int, window: int,
+                       min_match: int, match_policy: int, stream_bytes: int,
+                       tail: bytes = b"") -> bytes:
+    """The 64-byte header of a stream with these fields (host memory)."""
+    buf = ctypes.create_string_buffer(64)
+    st = lib().gpulz_write_header(buf, nbytes, symbol_bytes, chunk_symbols, window, min_match,
+                                  match_policy, stream_bytes, bytes(tail) if tail else None)
+    if st != GPULZ_OK:
+        raise GpulzError(st, "gpulz_write_header")
+    return buf.raw
+
+
+def gpulz_read_header(header: bytes) -> StreamInfo:
+    info = StreamInfo()
+    st = lib().gpulz_read_header(bytes(header), len(header), ctypes.byref(info))
+    if st != GPULZ_OK:
+        raise GpulzError(st, "gpulz_read_header")
+    return info
+
+
+def gpulz_record_offsets(d_table: int, chunks: int, d_offsets: int, stream: int = 0) -> int:
+    return lib().gpulz_record_offsets(d_table, chunks, d_offsets, stream)
 
 
 def gpulz_decompress_workspace_size(comp_bytes: int, nbytes: int = 0) -> int:

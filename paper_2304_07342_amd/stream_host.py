@@ -17,18 +17,21 @@ places with no second host copy.
 Decompression streams the same way: each block of chunks becomes a small
 standalone stream (its own header, its slice of the table and its records)
 that is decoded on the device and copied into the pinned output.
+
+The stream format stays in the library: headers are written and read by
+gpulz_write_header / gpulz_read_header, table and record positions come from
+gpulz_table_offset, and the record offsets of a stream from its table by the
+device scan gpulz_record_offsets.
 """
 from __future__ import annotations
 
 import os
-import struct
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
 from . import gpulz
 
-HEADER = 64
 _COPY_PIECE = 8 << 20
 
 
@@ -58,13 +61,6 @@ def block_plan(nbytes: int, S: int, C: int, block_bytes: int):
     if not out:
         out.append((0, nbytes, 0, 0))
     return out
-
-
-def header(n: int, S: int, C: int, W: int, MIN: int, policy: int, N: int, total: int,
-           tail: bytes) -> bytes:
-    h = b"GLZ1" + struct.pack("<HBBIHBBQQQB", 1, S, policy, C, W, MIN, 255, n, N, total,
-                              len(tail))
-    return h + bytes(7) + tail + bytes(8 - len(tail)) + bytes(8)
 
 
 def _host_bytes(x):
@@ -127,7 +123,8 @@ def compress_host(x, S: int, C: int, W: int, MIN: int, policy: int = 0,
     copied = [torch.cuda.Event() for _ in range(2)]   # its stream copied back
     used = [False, False]
     copier = _Copier(threads or default_threads())
-    rec_off = HEADER + 8 * N
+    at = gpulz.gpulz_table_offset
+    rec_off = at(N)  # the first record of the assembled stream
 
     def stage(k):
         off, nb, _, _ = blocks[k]
@@ -162,12 +159,12 @@ def compress_host(x, S: int, C: int, W: int, MIN: int, policy: int = 0,
         size, status = comps[j].result()
         if status != gpulz.GPULZ_OK:
             raise gpulz.GpulzError(status, "block compress")
-        rec = size - HEADER - 8 * nc
+        # the block's stream: header, its nc table entries, its records
+        rec = size - at(nc)
         body = comps[j].out
         with torch.cuda.stream(copy_out):
-            out_t[HEADER + 8 * c0:HEADER + 8 * (c0 + nc)].copy_(body[HEADER:HEADER + 8 * nc],
-                                                               non_blocking=True)
-            out_t[rec_off:rec_off + rec].copy_(body[HEADER + 8 * nc:size], non_blocking=True)
+            out_t[at(c0):at(c0 + nc)].copy_(body[at(0):at(nc)], non_blocking=True)
+            out_t[rec_off:rec_off + rec].copy_(body[at(nc):size], non_blocking=True)
             copied[j].record(copy_out)
         rec_off += rec
 
@@ -184,7 +181,8 @@ def compress_host(x, S: int, C: int, W: int, MIN: int, policy: int = 0,
         torch.cuda.synchronize()
     tail = src[n - n % S:].tobytes()
     out = out_t.numpy()
-    out[:HEADER] = np.frombuffer(header(n, S, C, W, MIN, policy, N, rec_off, tail), dtype=np.uint8)
+    hdr = gpulz.gpulz_write_header(n, S, C, W, MIN, policy, rec_off, tail)
+    out[:at(0)] = np.frombuffer(hdr, dtype=np.uint8)
     return out[:rec_off]
 
 
@@ -194,16 +192,22 @@ def decompress_host(stream, block_bytes: int | None = None,
     numpy array over pinned host memory."""
     import torch
     s, _ = _host_bytes(stream)
-    n, S, total = gpulz.gpulz_peek_header(s[:HEADER].tobytes())
-    if total != s.size:
+    at = gpulz.gpulz_table_offset
+    info = gpulz.gpulz_read_header(s[:at(0)].tobytes())
+    if info.stream_bytes != s.size:
         raise gpulz.GpulzError(gpulz.GPULZ_ERR_CORRUPT, "stream size")
-    policy = int(s[7])
-    C, W = struct.unpack_from("<IH", s, 8)
-    MIN = int(s[14])
-    N = int(struct.unpack_from("<Q", s, 24)[0])
-    r = int(s[40])
-    table = s[HEADER:HEADER + 8 * N].view(np.uint32).reshape(N, 2).astype(np.int64)
-    rec_start = HEADER + 8 * N + np.concatenate([[0], np.cumsum(table.sum(axis=1))])
+    n, S, C, W, MIN = (info.nbytes, info.symbol_bytes, info.chunk_symbols, info.window,
+                       info.min_match)
+    N, policy = info.chunks, info.match_policy
+    tail = bytes(info.tail[:info.tail_bytes])
+    # record offsets from the table, scanned on the device
+    table = torch.from_numpy(s[at(0):at(N)].copy()).cuda()
+    offs = torch.empty(N + 1, dtype=torch.int64, device="cuda")
+    gpulz._check(gpulz.gpulz_record_offsets(table.data_ptr(), N, offs.data_ptr(),
+                                            gpulz._stream_handle(torch.cuda.current_stream())),
+                 "gpulz_record_offsets")
+    rec_start = at(N) + offs.cpu().numpy()
+    del table, offs
     if int(rec_start[-1]) != s.size:
         raise gpulz.GpulzError(gpulz.GPULZ_ERR_CORRUPT, "record sizes")
     block_bytes = block_bytes or default_block_bytes()
@@ -212,8 +216,8 @@ def decompress_host(stream, block_bytes: int | None = None,
     for off, nb, c0, nc in blocks:
         last = c0 + nc == N
         nb_block = nb if last else nc * C * S
-        tot = HEADER + 8 * nc + int(rec_start[c0 + nc] - rec_start[c0])
-        hdr = header(nb_block, S, C, W, MIN, policy, nc, tot, s[48:48 + r].tobytes() if last else b"")
+        tot = at(nc) + int(rec_start[c0 + nc] - rec_start[c0])
+        hdr = gpulz.gpulz_write_header(nb_block, S, C, W, MIN, policy, tot, tail if last else b"")
         subs.append((off, nb_block, c0, nc, tot, hdr))
     smax = max(1, max(t for *_, t, _ in subs))
     bmax = max(1, max(b for _, b, *_ in subs))
@@ -237,9 +241,9 @@ def decompress_host(stream, block_bytes: int | None = None,
                 loaded[j].synchronize()
                 copy_in.wait_event(decoded[j])
             p = pin[j].numpy()
-            p[:HEADER] = np.frombuffer(hdr, dtype=np.uint8)
-            p[HEADER:HEADER + 8 * nc] = s[HEADER + 8 * c0:HEADER + 8 * (c0 + nc)]
-            copier(p[HEADER + 8 * nc:tot], s[rec_start[c0]:rec_start[c0 + nc]])
+            p[:at(0)] = np.frombuffer(hdr, dtype=np.uint8)
+            p[at(0):at(nc)] = s[at(c0):at(c0 + nc)]
+            copier(p[at(nc):tot], s[rec_start[c0]:rec_start[c0 + nc]])
             with torch.cuda.stream(copy_in):
                 dev_in[j][:tot].copy_(pin[j][:tot], non_blocking=True)
                 loaded[j].record(copy_in)

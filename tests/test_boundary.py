@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_status_strings():
-    assert gpulz.gpulz_abi_version() == 101
+    assert gpulz.gpulz_abi_version() == 102
     assert gpulz.status_string(0) == "ok"
     assert gpulz.status_string(3) == "corrupt stream"
     assert gpulz.status_string(99) == "unknown status"

@@ -51,3 +51,35 @@ def test_corrupt_record_in_one_block_is_reported():
     s[rec] ^= 0xFF   # its first flag byte: the token kinds no longer fit the payload size
     with pytest.raises(gpulz.GpulzError):
         stream_host.decompress_host(np.frombuffer(bytes(s), np.uint8), block_bytes=32 << 10)
+
+
+@pytest.mark.parametrize("n,S,C", [(0, 4, 16), (3000, 1, 7), (1_000_003, 4, 256), (4_000_000, 2, 64)])
+def test_record_offsets_scan_the_table(n, S, C):
+    """gpulz_record_offsets against the running sum of the oracle stream's
+    table entries."""
+    import torch
+    from paper_2304_07342_amd import gpulz
+    x = synth.mixed(n, S, seed=n)
+    s = np.frombuffer(oracle.compress(x, S, C, 64, 2), np.uint8)
+    N = -(-(n // S) // C)
+    print("record offsets", n, S, C, N, flush=True)
+    sizes = s[64:64 + 8 * N].view(np.uint32).reshape(N, 2).astype(np.uint64).sum(axis=1)
+    want = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    table = torch.from_numpy(s[64:64 + 8 * N].copy()).cuda()
+    got = torch.full((N + 1,), -1, dtype=torch.int64, device="cuda")
+    st = gpulz.gpulz_record_offsets(table.data_ptr(), N, got.data_ptr(),
+                                    torch.cuda.current_stream().cuda_stream)
+    assert st == gpulz.GPULZ_OK
+    assert np.array_equal(got.cpu().numpy().astype(np.uint64), want)
+    assert 64 + 8 * N + int(want[-1]) == s.size
+
+
+def test_record_sizes_must_cover_the_stream():
+    """The device scan of a corrupted table no longer ends at the stream's
+    end: decompress_host refuses before decoding any block."""
+    from paper_2304_07342_amd import gpulz
+    x = np.arange(4096, dtype=np.uint32)
+    s = bytearray(oracle.compress(x.tobytes(), 4, 256, 64, 2))
+    s[64] ^= 1    # first chunk's flag-byte count no longer matches the records
+    with pytest.raises(gpulz.GpulzError):
+        stream_host.decompress_host(np.frombuffer(bytes(s), np.uint8), block_bytes=4096)

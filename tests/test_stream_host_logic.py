@@ -21,18 +21,38 @@ def test_blocks_tile_the_input_on_chunk_boundaries(n, S, C, bb):
     assert chunk == -(-(n // S) // C)
 
 
-def test_header_layout():
-    h = stream_host.header(10, 4, 2, 8, 2, 1, 1, 99, b"\x01\x02")
-    assert len(h) == 64 and h[:4] == b"GLZ1" and h[6] == 4 and h[7] == 1 and h[40] == 2
-    assert h[48:50] == b"\x01\x02" and h[50:] == bytes(14)
-
-
-def test_record_sizes_must_cover_the_stream():
+@pytest.mark.parametrize("n,S,C,W,MIN,policy", [
+    (0, 4, 16, 8, 2, 0), (3, 4, 16, 8, 2, 0), (10, 4, 2, 8, 2, 1), (100003, 8, 100, 32, 1, 0),
+    (65537, 2, 1024, 128, 2, 0), (5000, 1, 256, 256, 3, 1)])
+def test_library_header_is_the_oracles(n, S, C, W, MIN, policy):
+    """gpulz_write_header against the header of the oracle's stream of the
+    same input (the oracle writes its own), and gpulz_read_header back."""
     import numpy as np
     import oracle
     from paper_2304_07342_amd import gpulz
-    x = np.arange(4096, dtype=np.uint32)
-    s = bytearray(oracle.compress(x.tobytes(), 4, 256, 64, 2))
-    s[64] ^= 1    # first chunk's flag-byte count no longer matches the records
+    x = np.random.default_rng(n).integers(0, 4, size=n, dtype=np.uint8)
+    s = oracle.compress(x.tobytes(), S, C, W, MIN, policy=policy)
+    tail = x[n - n % S:].tobytes()
+    assert gpulz.gpulz_write_header(n, S, C, W, MIN, policy, len(s), tail) == s[:64]
+    info = gpulz.gpulz_read_header(s[:64])
+    assert (info.nbytes, info.symbol_bytes, info.chunk_symbols, info.window, info.min_match,
+            info.match_policy, info.stream_bytes) == (n, S, C, W, MIN, policy, len(s))
+    assert info.chunks == -(-(n // S) // C) and bytes(info.tail[:info.tail_bytes]) == tail
+    assert gpulz.gpulz_table_offset(info.chunks) == 64 + 8 * info.chunks
+
+
+def test_read_header_rejects_what_the_decoder_rejects():
+    import oracle
+    from paper_2304_07342_amd import gpulz
+    h = bytearray(oracle.compress(bytes(range(200)) * 5, 2, 64, 32, 2)[:64])
+    assert gpulz.gpulz_read_header(bytes(h)).chunks == 8
+    for at, v in [(0, ord("X")), (4, 2), (6, 3), (7, 2), (15, 7), (24, 9), (40, 1), (44, 1),
+                  (60, 1)]:
+        bad = bytearray(h)
+        bad[at] = v
+        with pytest.raises(gpulz.GpulzError):
+            gpulz.gpulz_read_header(bytes(bad))
     with pytest.raises(gpulz.GpulzError):
-        stream_host.decompress_host(np.frombuffer(bytes(s), np.uint8), block_bytes=4096)
+        gpulz.gpulz_write_header(10, 3, 16, 8, 2, 0, 100)   # S = 3
+    with pytest.raises(gpulz.GpulzError):
+        gpulz.gpulz_write_header(10, 4, 16, 8, 2, 0, 70)    # smaller than header + table
