@@ -285,7 +285,7 @@ __device__ __forceinline__ void hit_step(const typename SymType<S>::T (&x)[16 / 
 // and every ring index is a constant.
 template <int S, bool kHead, int kStep>
 __device__ __forceinline__ void hit_block(const uint4* w4, uint32_t base, uint32_t W,
-                                          uint32_t* hits) {
+                                          uint32_t* hits, uint32_t kb = 1, uint32_t ke = ~0u) {
   using T = typename SymType<S>::T;
   constexpr int V = Geo<S>::V;
   constexpr int R = Geo<S>::R;
@@ -309,8 +309,15 @@ __device__ __forceinline__ void hit_block(const uint4* w4, uint32_t base, uint32
   const uint32_t kfull = W / V;            // steps whose V offsets are all <= W
   uint32_t k = 1;
   if constexpr (R == 1) {
+    // steps [kb, ke) only (the split parse shares one block's offsets among
+    // several waves); x0v is the vector after step k's
+    const uint32_t kend = min(ke, kfull + 1);  // full steps end
+    if (kb > 1) {
+      k = kb;
+      x0v = w4[vbase - (int)(kb - 1)];
+    }
     // two steps per round: ring slot 1 for odd k, 0 for even k
-    for (; k + 1 <= kfull; k += 2) {
+    for (; k + 1 < kend; k += 2) {
       ring[1] = w4[vbase - (int)k];
       ring[0] = w4[vbase - (int)k - 1];
       const uint4 w1[2] = {ring[1], x0v}, w2[2] = {ring[0], ring[1]};
@@ -318,14 +325,14 @@ __device__ __forceinline__ void hit_block(const uint4* w4, uint32_t base, uint32
       hit_step<S, kHead, false, kStep, R>(x, w2, V * k, V, base, acc);
       x0v = ring[0];
     }
-    if (k <= kfull) {
+    if (k < kend) {
       const uint4 q1 = w4[vbase - (int)k];
       const uint4 w1[2] = {q1, x0v};
       hit_step<S, kHead, false, kStep, R>(x, w1, V * (k - 1), V, base, acc);
       x0v = q1;
       ++k;
     }
-    if (W % V) {
+    if (W % V && k == kfull + 1 && k < ke) {
       const uint4 w1[2] = {w4[vbase - (int)k], x0v};
       hit_step<S, kHead, true, kStep, R>(x, w1, V * (k - 1), W % V, base, acc);
     }
@@ -938,9 +945,11 @@ __device__ __forceinline__ void extend_run(uint32_t& live, uint32_t& n, uint32_t
   }
 }
 
-// Greedy parse of a whole dense chunk [0, c) (1- and 2-byte symbols,
-// MIN <= 2), every position compared once with its window (StreamMatch's
-// packed layout). A token open at h with t positions matched either
+// Greedy parse of a dense chunk of c symbols (1- and 2-byte symbols,
+// MIN <= 2) from position h0, taking tokens that start before hend (the
+// last one may run past hend, up to c): [0, c) for the whole chunk, a
+// segment for the split parse. Every position is compared once with its
+// window (StreamMatch's packed layout). A token open at h with t positions matched either
 // survives position h + t (some offset still matches), or ends there: a
 // pointer (t, largest survivor) if t >= MIN, else a literal at h; either
 // way the next token starts at h + t (MIN <= 2), whose compare is the one
@@ -952,9 +961,10 @@ __device__ __forceinline__ void extend_run(uint32_t& live, uint32_t& n, uint32_t
 // Token descriptors are collected one per lane in dlo; flush(dlo) takes
 // each full group of 64. Returns the number of tokens left in dlo.
 template <int S, int WC, typename Flush>
-__device__ __forceinline__ uint32_t parse_dense(const uint8_t* stage, uint32_t c, uint32_t W,
-                                                uint32_t MIN, const uint64_t (&wmask64)[WC],
-                                                uint32_t lane, uint32_t& dlo, Flush&& flush) {
+__device__ __forceinline__ uint32_t parse_dense(const uint8_t* stage, uint32_t h0, uint32_t hend,
+                                                uint32_t c, uint32_t W, uint32_t MIN,
+                                                const uint64_t (&wmask64)[WC], uint32_t lane,
+                                                uint32_t& dlo, Flush&& flush) {
   using T = typename SymType<S>::T;
   using SM = StreamMatchFor<S, WC>;
   constexpr int NC = stream_cols(S, WC);
@@ -1002,9 +1012,11 @@ __device__ __forceinline__ uint32_t parse_dense(const uint8_t* stage, uint32_t c
   const uint32_t stage_lds = (uint32_t)(uintptr_t)stage;
   uint32_t z[NC];
   bool have_z = false;  // z holds position h's compare already
-  uint32_t h = 0;
+  // wave-uniform bounds (a caller may derive them from the wave index)
+  uint32_t h = __builtin_amdgcn_readfirstlane(h0);
+  hend = __builtin_amdgcn_readfirstlane(hend);
   uint32_t vq;  // next position to compare, in a vector register
-  asm volatile("v_mov_b32 %0, 0" : "=v"(vq));
+  asm volatile("v_mov_b32 %0, %1" : "=v"(vq) : "s"(h));
   // From each group-aligned token start the group loop (dense_groups) takes
   // over, until a flush, a capped token (redone here first, then the group
   // loop again) or the chunk's last groups (finished here).
@@ -1012,21 +1024,21 @@ __device__ __forceinline__ uint32_t parse_dense(const uint8_t* stage, uint32_t c
   bool fast_ok = true, skip_fast = false;
   uint32_t hi = 0;
   const uint32_t dk = (4 / S) * lane + 4 / S;  // largest offset of this lane in column 0
-  while (h < c) {
-    if (fast_ok && !skip_fast && (h & (kPh - 1)) == 0 && h + kPh < c) {
+  while (h < hend) {
+    if (fast_ok && !skip_fast && (h & (kPh - 1)) == 0 && h + kPh < hend) {
       uint32_t q = h, hh = h, t = 0, tlim = 0, code;
       uint32_t lv[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) lv[j] = 0;
       for (;;) {
         nb = __builtin_amdgcn_readfirstlane(nb);  // uniform (the compiler cannot tell)
-        code = dense_groups<S, NC>(q, hh, t, tlim, nb, lv, lo, hi, c, W, MIN, stage_lds,
+        code = dense_groups<S, NC>(q, hh, t, tlim, nb, lv, lo, hi, c, hend, W, MIN, stage_lds,
                                    (uint32_t)woff[0], lane, dk, wm, SM::P::kLive);
         if (code != kDenseFlush) break;
         flush(lo);
         lo = hi;
         nb -= 64;
-        if (q + kPh >= c) {
+        if (q + kPh >= hend) {
           code = kDenseTail;
           break;
         }
@@ -1451,8 +1463,8 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
   uint32_t p = 0;
   if constexpr (kStreamSearch<S>) {
     if (dense && job.MIN <= 2) {
-      const uint32_t rest = parse_dense<S, WC>(stage, c, job.W, job.MIN, wmask, lane, desc,
-                                               [&](uint32_t d64) {
+      const uint32_t rest = parse_dense<S, WC>(stage, 0, c, c, job.W, job.MIN, wmask, lane,
+                                               desc, [&](uint32_t d64) {
         emit_group<S, kSinglePass>(64, d64, ntok >> 6, win, slot, job.flag_area, pay, g0);
         ntok += 64;
       });
@@ -1589,8 +1601,51 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
   for (uint32_t k = tid; k < 4 * tw; k += blockDim.x) tok[k] = 0;
   __syncthreads();
   const bool sampled = job.MIN >= 2;
-  build_hits<S, WC>(stage, wave, (c + kBlock - 1) / kBlock, nwaves, job.W, c, sampled, hits);
+  const uint32_t nblocks = (c + kBlock - 1) / kBlock;
+  if constexpr (Geo<S>::R == 1) {
+    // fewer blocks than waves: the waves of one block split its window
+    // offsets (steps [kb, ke) each) and OR their hits into the bitmap
+    constexpr uint32_t V = Geo<S>::V;
+    const uint32_t nsplit = min(8u, max(1u, nwaves / max(1u, nblocks)));
+    const uint32_t kmax = job.W / V + (job.W % V ? 1u : 0u);
+    const uint4* w4 = reinterpret_cast<const uint4*>(stage);
+    for (uint32_t u = wave; u < nblocks * nsplit; u += nwaves) {
+      const uint32_t b = u / nsplit, part = u % nsplit;
+      const uint32_t kb = 1 + part * kmax / nsplit, ke = 1 + (part + 1) * kmax / nsplit;
+      if (kb >= ke) continue;
+      const uint32_t base = b * kBlock;
+      if (sampled) {
+        if (base >= job.W) hit_block<S, false, 2>(w4, base, job.W, hits, kb, ke);
+        else hit_block<S, true, 2>(w4, base, job.W, hits, kb, ke);
+      } else {
+        if (base >= job.W) hit_block<S, false, 1>(w4, base, job.W, hits, kb, ke);
+        else hit_block<S, true, 1>(w4, base, job.W, hits, kb, ke);
+      }
+    }
+  } else {
+    build_hits<S, WC>(stage, wave, nblocks, nwaves, job.W, c, sampled, hits);
+  }
   __syncthreads();
+  // match-dense chunks (1- and 2-byte symbols, MIN <= 2): at least 3/4 of the
+  // tested positions hit; their segments take the streaming parse
+  bool dense = false;
+  if constexpr (kStreamSearch<S>) {
+    if (job.MIN <= 2) {
+      if (wave == 0) {
+        uint32_t cnt = 0;
+        for (uint32_t k = lane; k < (c + 31) / 32; k += 64) {
+          uint32_t wd = hits[k];
+          if (32 * k + 32 > c) wd &= (1u << (c - 32 * k)) - 1u;
+          cnt += (uint32_t)__popc(wd);
+        }
+        cnt = readlane(wave_incl_scan(cnt), 63);
+        const uint32_t tested = sampled ? (c + 1) / 2 : c;
+        if (lane == 0) pc_tok[0] = 4 * cnt >= 3 * tested;
+      }
+      __syncthreads();
+      dense = pc_tok[0] != 0;
+    }
+  }
 
   const T* win = reinterpret_cast<const T*>(stage);
   uint64_t wmask[WC];
@@ -1601,7 +1656,33 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
   sm.init(stage, job.W, lane);
 
   // ---- each wave: the greedy parse of its own segment
-  {
+  if constexpr (kStreamSearch<S>) {
+    if (dense) {
+      // the streaming parse of the segment; each group of token descriptors
+      // becomes token and pointer bits and (L, d) at the tokens' positions
+      // (a token's position: the segment start plus the lengths before it)
+      const uint32_t s0 = min(c, wave * seg), s1 = min(c, s0 + seg);
+      uint32_t gpos = s0, dlo = 0;
+      auto mark = [&](uint32_t d, uint32_t cnt) {
+        const bool v = lane < cnt;
+        const bool isp = v && (d & 1u);
+        const uint32_t len = !v ? 0u : (isp ? (d >> 1) & 0xFFu : 1u);
+        const uint32_t incl = wave_incl_scan(len);
+        const uint32_t pos = gpos + incl - len;
+        if (v) atomicOr(&tok[pos >> 5], 1u << (pos & 31u));
+        if (isp) {
+          atomicOr(&ptr[pos >> 5], 1u << (pos & 31u));
+          tinfo[pos] = (uint16_t)((((d >> 1) & 0xFFu) << 8) | ((d >> 9) & 0xFFu));
+        }
+        gpos += readlane(incl, 63);
+      };
+      const uint32_t rest = parse_dense<S, WC>(stage, s0, s1, c, job.W, job.MIN, wmask, lane, dlo,
+                                               [&](uint32_t d64) { mark(d64, 64); });
+      mark(dlo, rest);
+      if (lane == 0) ends[wave] = gpos;
+    }
+  }
+  if (!dense) {
     const uint32_t s0 = min(c, wave * seg), s1 = min(c, s0 + seg);
     uint32_t p = s0;
     CandCursor cc;
