@@ -52,8 +52,8 @@ HBM_PEAK_GBPS = 8000.0
 # "prep" is the compress call's preparation kernel (look-back descriptors
 # and tickets zeroed); the step is prep + encode.
 ENCODE_COUNTERS = {
-    "sources_sha256": "1376381409e78c9ba0a7e0355f23d745a087fadda04c77a186e8b53384870056",
-    "fetch_kib": 140671.4, "write_kib": 277038.5,
+    "sources_sha256": "87241facae1ccfc00aaa0f2c7a141b4048ec80d174408c0db2f760178acfb540",
+    "fetch_kib": 140085.9, "write_kib": 277147.4,
     "prep_fetch_kib": 16.0, "prep_write_kib": 128.3,
     "fetch_scale": 2.0, "write_scale": 1.0,
 }
