@@ -1418,8 +1418,9 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
   // candidate still gets the exact search).
   //
   // Dense chunks (streaming search, one wave per chunk): the streaming
-  // search compares every position it passes anyway, so the bitmap only
-  // pays where it lets the parse skip literal runs. If at least 3/4 of the
+  // search compares every position it passes anyway, at a fixed cost per
+  // position, while the per-candidate search costs several times that, so
+  // the bitmap only pays where candidates are rare. If at least 1/4 of the
   // tested positions of the first block are hits, the rest of the bitmap is
   // not built and every position is a candidate.
   const bool sampled = job.MIN >= 2;
@@ -1436,7 +1437,7 @@ __device__ void encode_chunk(const ChunkJob& job, uint8_t* lds) {
         constexpr uint32_t kWords = kBlock / 32;
         const uint32_t cnt = lane < kWords ? (uint32_t)__popc(hits[lane]) : 0u;
         const uint32_t tested = sampled ? kBlock / 2 : kBlock;
-        dense = 4 * readlane(wave_incl_scan(cnt), 63) >= 3 * tested;
+        dense = 4 * readlane(wave_incl_scan(cnt), 63) >= tested;
         b0 = dense ? nblocks : 1;
       }
     }
@@ -1626,7 +1627,7 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
     build_hits<S, WC>(stage, wave, nblocks, nwaves, job.W, c, sampled, hits);
   }
   __syncthreads();
-  // match-dense chunks (1- and 2-byte symbols, MIN <= 2): at least 3/4 of the
+  // match-dense chunks (1- and 2-byte symbols, MIN <= 2): at least 1/4 of the
   // tested positions hit; their segments take the streaming parse
   bool dense = false;
   if constexpr (kStreamSearch<S>) {
@@ -1640,7 +1641,7 @@ __device__ void encode_chunk_spec(const ChunkJob& job, uint8_t* lds) {
         }
         cnt = readlane(wave_incl_scan(cnt), 63);
         const uint32_t tested = sampled ? (c + 1) / 2 : c;
-        if (lane == 0) pc_tok[0] = 4 * cnt >= 3 * tested;
+        if (lane == 0) pc_tok[0] = 4 * cnt >= tested;
       }
       __syncthreads();
       dense = pc_tok[0] != 0;
