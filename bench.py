@@ -625,7 +625,7 @@ def batch_leg(args):
     pool_bytes = args.pool_mib << 20
     spec = synth.batch_spec(args.nbufs, seed=3, pool_bytes=pool_bytes)
     pools = pools_on_device(list(synth.POOL_KINDS), pool_bytes)
-    tuned = autotune_widths(pools, 32 << 20, log)
+    tuned = autotune_widths(pools, 64 << 20, log)
     inputs = [pools[kind][off:off + n] for kind, S, off, n in spec]
     widths = [S for _, S, _, _ in spec]
     total = sum(n for _, _, _, n in spec)

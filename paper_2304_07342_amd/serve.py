@@ -340,7 +340,7 @@ def main_bench(args):
     for i, kind in enumerate(synth.POOL_KINDS):
         log(f"pool {kind}")
         pools[kind] = torch.from_numpy(synth.POOL_KINDS[kind][1](pool_bytes, 100 + i)[:pool_bytes]).cuda()
-    autotune.tune({S: pools[k[0]][: 32 << 20] for S, k in synth.WIDTH_KINDS.items()}, log=log)
+    autotune.tune({S: pools[k[0]][: 64 << 20] for S, k in synth.WIDTH_KINDS.items()}, log=log)
     # streams for decompress requests: compress a set of log-uniform slices once
     rng = np.random.Generator(np.random.PCG64(44))
     srcs, widths = [], []
