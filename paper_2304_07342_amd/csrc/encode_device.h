@@ -1033,7 +1033,7 @@ __device__ __forceinline__ uint32_t parse_dense(const uint8_t* stage, uint32_t h
       for (;;) {
         nb = __builtin_amdgcn_readfirstlane(nb);  // uniform (the compiler cannot tell)
         code = dense_groups<S, NC>(q, hh, t, tlim, nb, lv, lo, hi, c, hend, W, MIN, stage_lds,
-                                   (uint32_t)woff[0], lane, dk, wm, SM::P::kLive);
+                                   (uint32_t)woff[0], dk, wm, SM::P::kLive);
         if (code != kDenseFlush) break;
         flush(lo);
         lo = hi;
