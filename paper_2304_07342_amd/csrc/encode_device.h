@@ -449,13 +449,16 @@ __device__ __forceinline__ void stage_chunk(const ChunkJob& job, uint8_t* stage)
     const uint32_t full = (uint32_t)min<uint64_t>(nw, job.src_avail / 16);
     const uint32_t step = blockDim.x;
     uint32_t k = tid;
+    // (four named vectors, not an array: an array here has been left in
+    // scratch memory inside the persistent batch encoder)
     for (; k + 3 * step < full; k += 4 * step) {
-      uint4 v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        v[u] = *reinterpret_cast<const uint4*>(job.src + 16ull * (k + u * step));
-#pragma unroll
-      for (int u = 0; u < 4; ++u) *reinterpret_cast<uint4*>(stage + 16 * (k + u * step)) = v[u];
+      const uint4* src = reinterpret_cast<const uint4*>(job.src) + k;
+      const uint4 v0 = src[0], v1 = src[step], v2 = src[2 * step], v3 = src[3 * step];
+      uint4* dst = reinterpret_cast<uint4*>(stage) + k;
+      dst[0] = v0;
+      dst[step] = v1;
+      dst[2 * step] = v2;
+      dst[3 * step] = v3;
     }
     for (; k < nw; k += step) {
       const uint64_t g = 16ull * k;
