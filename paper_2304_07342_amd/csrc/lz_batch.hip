@@ -156,8 +156,11 @@ __device__ __forceinline__ void encode_item(const BatchEncArgs& a, uint64_t b, c
 
 // Persistent encoder for the chunks of symbol width S (width index WI); the
 // window spans WC columns of 64 offsets (one window per width in a batch).
+// At least 6 waves per SIMD: the 1-byte encoder then fits in 80 VGPRs (82
+// otherwise, 5 waves) without spilling; the other widths need fewer.
 template <int S, uint32_t WI, int WC>
-__global__ __launch_bounds__(64 * enc::kEncodeWaves) void batch_encode_kernel(BatchEncArgs a) {
+__global__ __launch_bounds__(64 * enc::kEncodeWaves) __attribute__((amdgpu_waves_per_eu(6)))
+void batch_encode_kernel(BatchEncArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ uint64_t item;
   const uint64_t T = a.ctrl->T[WI];
