@@ -1023,12 +1023,13 @@ __device__ __forceinline__ uint32_t parse_dense(const uint8_t* stage, uint32_t h
   // From each group-aligned token start the group loop (dense_groups) takes
   // over, until a flush, a capped token (redone here first, then the group
   // loop again) or the chunk's last groups (finished here).
-  constexpr uint32_t kPh = 4 / S;  // positions per dword group
+  constexpr uint32_t kPh = 4 / S;  // positions per dword
+  constexpr uint32_t kGp = kDenseGroupPositions;  // positions per group of the loop
   bool fast_ok = true, skip_fast = false;
   uint32_t hi = 0;
   const uint32_t dk = (4 / S) * lane + 4 / S;  // largest offset of this lane in column 0
   while (h < hend) {
-    if (fast_ok && !skip_fast && (h & (kPh - 1)) == 0 && h + kPh < hend) {
+    if (fast_ok && !skip_fast && (h & (kPh - 1)) == 0 && h + kGp < hend) {
       uint32_t q = h, hh = h, t = 0, tlim = 0, code;
       uint32_t lv[NC];
 #pragma unroll
@@ -1041,7 +1042,7 @@ __device__ __forceinline__ uint32_t parse_dense(const uint8_t* stage, uint32_t h
         flush(lo);
         lo = hi;
         nb -= 64;
-        if (q + kPh >= hend) {
+        if (q + kGp >= hend) {
           code = kDenseTail;
           break;
         }
