@@ -1024,7 +1024,7 @@ __device__ __forceinline__ uint32_t parse_dense(const uint8_t* stage, uint32_t h
   // over, until a flush, a capped token (redone here first, then the group
   // loop again) or the chunk's last groups (finished here).
   constexpr uint32_t kPh = 4 / S;  // positions per dword
-  constexpr uint32_t kGp = kDenseGroupPositions;  // positions per group of the loop
+  constexpr uint32_t kGp = kDenseGroupPositions<S>;  // positions per group of the loop
   bool fast_ok = true, skip_fast = false;
   uint32_t hi = 0;
   const uint32_t dk = (4 / S) * lane + 4 / S;  // largest offset of this lane in column 0
