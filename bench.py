@@ -54,8 +54,8 @@ HBM_PEAK_GBPS = 8000.0
 # "prep" is the compress call's preparation kernel (look-back descriptors
 # and tickets zeroed); the step is prep + encode.
 ENCODE_COUNTERS = {
-    "sources_sha256": "43053760a19c00b7abaaccc95f73ae79d238300d0333cd2c6cdb28e37690056b",
-    "fetch_kib": 139865.1, "write_kib": 277151.0,
+    "sources_sha256": "2d96b58d2cec28f720430b5cc2d49e536ba57dc09fd90b1ae079cd0f15622aab",
+    "fetch_kib": 140127.6, "write_kib": 277144.8,
     "prep_fetch_kib": 16.0, "prep_write_kib": 128.3,
     "fetch_scale": 2.0, "write_scale": 1.0,
 }
